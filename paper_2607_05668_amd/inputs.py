@@ -1,0 +1,284 @@
+"""Seeded synthetic inputs shared by the HIP path and the CPU oracle.
+
+This module holds input data only: a counter-free pseudo-random generator,
+random Fourier-mode fields with their analytic gradients, the closed-form
+initial fields of each workload, and the workload presets as plain numbers.
+It contains none of the scheme's arithmetic (no equilibria, fluxes,
+collision or streaming), so importing it on either side shares no method
+code.  It imports numpy only.
+
+Generator: SplitMix64 (G. Steele, D. Lea, C. Flood, "Fast splittable
+pseudorandom number generators", OOPSLA 2014), written from its published
+description: add the golden-gamma increment to the state, then apply the
+two xor-shift-multiply finalisation rounds.  Doubles in [0,1) take the top
+53 bits.
+
+Random Fourier fields: ``sum_m A_m cos(2 pi (kx x + ky y) + phi_m)`` with
+integer wavenumbers ``k = floor(u (2K+1)) - K`` drawn per component, the
+pair (0,0) rejected, and ``phi = 2 pi u``.  Grid nodes sit at ``x_j = j/N``
+on the periodic unit square (the paper's periodic domains, Sec. 3).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_MASK = (1 << 64) - 1
+_GAMMA = 0x9E3779B97F4A7C15
+
+
+class SplitMix64:
+    """SplitMix64 stream; ``next_u64`` and ``next_double`` in [0, 1)."""
+
+    def __init__(self, seed: int):
+        self.state = seed & _MASK
+
+    def next_u64(self) -> int:
+        self.state = (self.state + _GAMMA) & _MASK
+        z = self.state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK
+        return z ^ (z >> 31)
+
+    def next_double(self) -> float:
+        return (self.next_u64() >> 11) * (1.0 / 9007199254740992.0)
+
+
+@dataclass(frozen=True)
+class Modes:
+    kx: tuple
+    ky: tuple
+    phi: tuple
+    amp: tuple
+
+
+def draw_modes(seed: int, nmodes: int, kmax: int, amp_per_mode: float) -> Modes:
+    """Draw ``nmodes`` (kx, ky, phase) triples with |k|_inf <= kmax, k != 0."""
+    rng = SplitMix64(seed)
+    kx, ky, ph = [], [], []
+    while len(kx) < nmodes:
+        a = int(math.floor(rng.next_double() * (2 * kmax + 1))) - kmax
+        b = int(math.floor(rng.next_double() * (2 * kmax + 1))) - kmax
+        if a == 0 and b == 0:
+            continue
+        kx.append(a)
+        ky.append(b)
+        ph.append(2.0 * math.pi * rng.next_double())
+    return Modes(tuple(kx), tuple(ky), tuple(ph), tuple([amp_per_mode] * nmodes))
+
+
+def grid2(n: int):
+    """Node coordinates (X, Y), each [n, n] with X varying along the last axis."""
+    x = np.arange(n, dtype=np.float64) / n
+    return np.meshgrid(x, x, indexing="xy")
+
+
+def grid3(n: int):
+    """Node coordinates (X, Y, Z), each [n, n, n] indexed [z, y, x]."""
+    x = np.arange(n, dtype=np.float64) / n
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    return X, Y, Z
+
+
+def fourier_field(n: int, modes: Modes):
+    """Return (value, d/dx, d/dy) of the mode sum on the n x n grid, [n, n] each."""
+    X, Y = grid2(n)
+    v = np.zeros((n, n))
+    gx = np.zeros((n, n))
+    gy = np.zeros((n, n))
+    two_pi = 2.0 * math.pi
+    for a, b, p, A in zip(modes.kx, modes.ky, modes.phi, modes.amp):
+        arg = two_pi * (a * X + b * Y) + p
+        v += A * np.cos(arg)
+        s = -A * np.sin(arg) * two_pi
+        gx += s * a
+        gy += s * b
+    return v, gx, gy
+
+
+# --------------------------------------------------------------------------
+# Workload presets (plain numbers).  f, tau_R, g_tau are the paper's
+# convergence-study recipes (supplement, numerical configuration table):
+# dt = f dx (acoustic) or f dx^2 (diffusive), tau_LB = 1/2 + tau_R dt,
+# tau_grad = g_tau dt, tracker collision rate 1/(g_tau + 1).
+# --------------------------------------------------------------------------
+
+@dataclass(frozen=True)
+class Preset:
+    name: str
+    system: str
+    lattice: str
+    n: int
+    storage: str
+    steps: int
+    scaling: str            # "acoustic" | "diffusive"
+    f: float
+    tau_r: float
+    g_tau: float | None
+    params: dict = field(default_factory=dict)
+
+
+PRESETS = {
+    "advdiff64": Preset("advdiff64", "advdiff_trk2d", "D2Q5", 64, "f64", 200,
+                        "diffusive", 1.9, 50.0, 6.0,
+                        {"ax": 0.1, "ay": 0.05, "nu": 0.01, "R": 0.0}),
+    "swe1024": Preset("swe1024", "swe2d", "D2Q9", 1024, "f32", 1000,
+                      "acoustic", 0.2, 2.0, None, {"g": 1.0}),
+    "nsf256": Preset("nsf256", "nsf3d_trk17", "D3Q7", 256, "f32", 500,
+                     "acoustic", 0.05, 20.0, 3.0, {}),
+    "sweadj512": Preset("sweadj512", "swe2d", "D2Q9", 512, "f32", 500,
+                        "acoustic", 0.2, 2.0, None, {"g": 1.0}),
+    "neohooke2048": Preset("neohooke2048", "neohooke2d", "D2Q9", 2048, "f16", 2000,
+                           "acoustic", 0.1, 2.0, None,
+                           {"rho0": 1.0, "mu_s": 1.0, "lambda_s": 2.0}),
+}
+
+# Seeds of the random fields.
+SEED_SWE_H = 1
+SEED_SWE_TARGET = 2
+SEED_TOPOGRAPHY = 3
+SEED_FD_DIRECTIONS = 4
+SEED_DISPLACEMENT = (5, 6)
+
+
+# --------------------------------------------------------------------------
+# Initial fields, SoA [K, ...] float64.
+# --------------------------------------------------------------------------
+
+def advdiff_initial(n: int):
+    """u0 = 1 + 0.1 sin(2 pi x) sin(2 pi y) and its analytic gradient, [3, n, n]."""
+    X, Y = grid2(n)
+    k = 2.0 * math.pi
+    u = 1.0 + 0.1 * np.sin(k * X) * np.sin(k * Y)
+    gx = 0.1 * k * np.cos(k * X) * np.sin(k * Y)
+    gy = 0.1 * k * np.sin(k * X) * np.cos(k * Y)
+    return np.stack([u, gx, gy])
+
+
+def advdiff_exact(n: int, t: float, ax: float, ay: float, nu: float):
+    """Closed-form decaying solution of u_t + a.grad u = nu lap u and its gradient."""
+    X, Y = grid2(n)
+    k = 2.0 * math.pi
+    d = math.exp(-2.0 * k * k * nu * t)
+    sx, cx = np.sin(k * (X - ax * t)), np.cos(k * (X - ax * t))
+    sy, cy = np.sin(k * (Y - ay * t)), np.cos(k * (Y - ay * t))
+    u = 1.0 + 0.1 * d * sx * sy
+    return np.stack([u, 0.1 * d * k * cx * sy, 0.1 * d * k * sx * cy])
+
+
+def swe_height(n: int, seed: int = SEED_SWE_H, h0: float = 1.0):
+    """h = h0 + sum of 8 random modes of amplitude 0.05 each, |k|_inf <= 8."""
+    m = draw_modes(seed, 8, 8, 0.05)
+    v, _, _ = fourier_field(n, m)
+    return h0 + v
+
+
+def swe_initial(n: int, seed: int = SEED_SWE_H):
+    """(h, hu, hv) with fluid at rest, [3, n, n]."""
+    h = swe_height(n, seed)
+    z = np.zeros_like(h)
+    return np.stack([h, z, z])
+
+
+def topography_gradient(n: int, seed: int = SEED_TOPOGRAPHY):
+    """b = grad z_b, z_b = sum of 8 modes of amplitude 0.01/8, |k|_inf <= 4; [2, n, n]."""
+    m = draw_modes(seed, 8, 4, 0.01 / 8.0)
+    _, gx, gy = fourier_field(n, m)
+    return np.stack([gx, gy])
+
+
+def neohooke_initial(n: int, seeds=SEED_DISPLACEMENT):
+    """F = I + grad w, v = 0 for a random displacement w; [6, n, n] as (F00,F01,F10,F11,v0,v1)."""
+    out = np.zeros((6, n, n))
+    for a, s in enumerate(seeds):
+        m = draw_modes(s, 8, 4, 0.01 / 8.0)
+        _, dx, dy = fourier_field(n, m)
+        out[2 * a + 0] = (1.0 if a == 0 else 0.0) + dx   # F_a0 = delta_a0 + d w_a / dx
+        out[2 * a + 1] = (1.0 if a == 1 else 0.0) + dy   # F_a1 = delta_a1 + d w_a / dy
+    return out
+
+
+# ----- 3D compressible NSF manufactured solution (shape of the paper's
+# homogenized-NSF MMS, supplement, with porosity 1) --------------------------
+
+@dataclass(frozen=True)
+class NsfMms:
+    gamma: float = 1.4
+    rho0: float = 1.0
+    p0: float = 1.0
+    mach: float = 0.1
+    reynolds: float = 100.0
+    prandtl: float = 0.71
+    amp: float = 0.05
+
+    @property
+    def cbar2(self):            # mean adiabatic sound speed squared, gamma p0 / rho0
+        return self.gamma * self.p0 / self.rho0
+
+    @property
+    def u0(self):               # per-axis drift
+        return self.mach * math.sqrt(self.cbar2)
+
+    @property
+    def mu(self):               # dynamic viscosity from Re = rho0 U0 L / mu, L = 1
+        return self.rho0 * self.u0 / self.reynolds
+
+    @property
+    def kappa(self):            # heat-flux coefficient mu c_p / Pr with c_p = gamma/(gamma-1), R = 1
+        return self.mu * self.gamma / (self.gamma - 1.0) / self.prandtl
+
+    @property
+    def E0(self):
+        return self.p0 / (self.gamma - 1.0) + 1.5 * self.rho0 * self.u0 ** 2
+
+    def reference(self):
+        """Background state (rho, rho u, E, trackers = 0), 17 values."""
+        q = np.zeros(17)
+        q[0] = self.rho0
+        q[1:4] = self.rho0 * self.u0
+        q[4] = self.E0
+        return q
+
+
+def nsf_exact(n: int, t: float, mms: NsfMms = NsfMms()):
+    """Exact fields [17, n, n, n] (indexed [k, z, y, x]) at time t.
+
+    Order: rho, rho u (3), E, G_ab = d_b u_a (9, index 5 + 3a + b), grad T (3).
+    """
+    X, Y, Z = grid3(n)
+    k = 2.0 * math.pi
+    A, p0, c2 = mms.amp, mms.p0, mms.cbar2
+    sx, cx = np.sin(k * X), np.cos(k * X)
+    sy, cy = np.sin(k * Y), np.cos(k * Y)
+    sz, cz = np.sin(k * Z), np.cos(k * Z)
+    st, ct = math.sin(t), math.cos(t)
+    U0 = mms.u0
+    rho = mms.rho0 + A * sx * cy * sz * ct
+    u = [U0 + A * cx * sy * sz * st,
+         U0 + A * sx * cy * sz * st,
+         U0 + A * sx * sy * cz * st]
+    p = p0 + c2 * (rho - mms.rho0) + A * p0 * cx * sy * cz * st
+    E = p / (mms.gamma - 1.0) + 0.5 * rho * (u[0] ** 2 + u[1] ** 2 + u[2] ** 2)
+    # gradients of u (rows a, columns b = d/dx_b)
+    Ak = A * k * st
+    du = [[-Ak * sx * sy * sz, Ak * cx * cy * sz, Ak * cx * sy * cz],
+          [Ak * cx * cy * sz, -Ak * sx * sy * sz, Ak * sx * cy * cz],
+          [Ak * cx * sy * cz, Ak * sx * cy * cz, -Ak * sx * sy * sz]]
+    drho = [A * k * ct * cx * cy * sz, -A * k * ct * sx * sy * sz, A * k * ct * sx * cy * cz]
+    dpi = [-A * p0 * k * st * sx * sy * cz, A * p0 * k * st * cx * cy * cz,
+           -A * p0 * k * st * cx * sy * sz]
+    T = p / rho
+    out = np.zeros((17, n, n, n))
+    out[0] = rho
+    for a in range(3):
+        out[1 + a] = rho * u[a]
+    out[4] = E
+    for a in range(3):
+        for b in range(3):
+            out[5 + 3 * a + b] = du[a][b]
+    for b in range(3):
+        dp = c2 * drho[b] + dpi[b]
+        out[14 + b] = (dp - T * drho[b]) / rho
+    return out
