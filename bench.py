@@ -1,0 +1,236 @@
+#!/usr/bin/env python3
+"""Throughput of the fused collide-and-stream step on one MI355X.
+
+Workload (one "step" = one fused collide-and-stream launch over the whole
+grid: load, moments, flux, equilibrium, sources, BGK, streamed store):
+shallow water (h, hu, hv), D2Q9 populations per field, 1024 x 1024
+periodic, FP32 shifted populations, synthetic seeded initial depth (8 random
+Fourier modes of amplitude 0.05, |k| <= 8, fluid at rest), g = 1,
+dt = 0.2 dx, tau = 1/2 + 2 dt.  Inputs are resident in HBM before the timed
+region.
+
+Printed: one JSON line with MLUPS x variables (the metric), the HBM
+roofline of the step kernel (algorithmic 2*K*Q*4 = 216 bytes per cell
+update over the kernel's average duration from HIP events recorded around
+every launch on the stream the kernel runs on), the FP64 CPU oracle on a
+bounded sample of the same workload, and the adjoint/forward time ratio of
+the checkpointed shallow-water rollout (512^2, 500 steps, snapshot every 50).
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E nameplate
+KERNEL_SOURCES = ["paper_2607_05668_amd/csrc/kernels.hip", "paper_2607_05668_amd/csrc/systems.hpp",
+                  "paper_2607_05668_amd/csrc/lattices.hpp", "paper_2607_05668_amd/csrc/impl.hpp",
+                  "paper_2607_05668_amd/csrc/dual.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_swe1024.json")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
+    were taken on the current kernel sources; else None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def time_steps(torch, g, k, per_launch):
+    """Run k steps on the stepper's stream; returns (total_ms, mean kernel ms)."""
+    st = g.stream
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(k)] \
+        if per_launch else []
+    torch.cuda.synchronize()
+    t0.record(st)
+    if per_launch:
+        for a, b in evs:
+            a.record(st)
+            g.step(1)
+            b.record(st)
+    else:
+        g.step(k)
+    t1.record(st)
+    torch.cuda.synchronize()
+    total = t0.elapsed_time(t1)
+    kern = sum(a.elapsed_time(b) for a, b in evs) / k if per_launch else total / k
+    return total, kern
+
+
+def cpu_baseline(target_s=10.0):
+    import numpy as np
+    import oracle
+    from paper_2607_05668_amd import inputs
+    p = inputs.PRESETS["swe1024"]
+    o = oracle.make(p, Q0=[1.0, 0.0, 0.0])
+    o.init(inputs.swe_initial(p.n))
+    t = time.perf_counter()
+    o.step(1)
+    one = time.perf_counter() - t
+    n = max(1, min(200, int(target_s / max(one, 1e-3))))
+    t = time.perf_counter()
+    o.step(n)
+    dt = time.perf_counter() - t
+    cells = p.n * p.n
+    assert np.isfinite(o.moments()).all()
+    return {"value": round(cells * n * 3 / dt / 1e6, 3), "unit": "MLUPS x variables", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"FP64 C oracle, same 1024x1024 D2Q9 shallow-water workload, {n} steps ({dt:.1f} s)"}
+
+
+def adjoint_ratio(torch):
+    from paper_2607_05668_amd import inputs, rollout
+    p = inputs.PRESETS["sweadj512"]
+    run = rollout.SweRollout(n=p.n, steps=p.steps, ckpt=50)
+    h0 = torch.tensor(inputs.swe_height(p.n), device="cuda")
+    b = torch.tensor(inputs.topography_gradient(p.n), device="cuda", dtype=torch.float32)
+    tgt = torch.tensor(inputs.swe_height(p.n, seed=inputs.SEED_SWE_TARGET), device="cuda")
+    hN = run.forward(h0, b)                      # warm-up
+    run.backward((hN - tgt) / hN.numel())
+    torch.cuda.synchronize()
+    reps = 3
+    fw = bw = 0.0
+    for _ in range(reps):
+        t = time.perf_counter()
+        hN = run.forward(h0, b)
+        torch.cuda.synchronize()
+        fw += time.perf_counter() - t
+        g = (hN - tgt) / hN.numel()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        run.backward(g)
+        torch.cuda.synchronize()
+        bw += time.perf_counter() - t
+    return {"adjoint_forward_ratio": round(bw / fw, 3), "forward_ms": round(1e3 * fw / reps, 3),
+            "backward_ms": round(1e3 * bw / reps, 3),
+            "workload": "swe2d D2Q9 512x512 FP32, 500 steps, snapshot every 50, topography source; "
+                        "backward = recompute with moment history + adjoint steps"}
+
+
+def probe_peak(torch, lbm):
+    n = 4 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty(n, dtype=torch.uint8, device="cuda")
+    lbm.bw_copy(b, a, n)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        lbm.bw_copy(b, a, n)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return round(2 * n / ms / 1e6, 1)
+
+
+def extra_runs(torch, lbm, inputs):
+    out = {}
+
+    def one(name, preset, n, storage, steps, bytes_per_cell, init):
+        g = lbm.from_preset(preset, n=n, storage=storage)
+        g.init(init)
+        g.step(10)
+        total, kern = time_steps(torch, g, steps, per_launch=False)
+        cells = g.C
+        out[name] = {"mlups": round(cells / kern / 1e3, 1), "mlups_x_vars": round(cells * g.K / kern / 1e3, 1),
+                     "ms_per_step": round(kern, 5), "algorithmic_GBps": round(bytes_per_cell * cells / kern / 1e6, 1)}
+        del g
+
+    p = inputs.PRESETS["swe1024"]
+    one("swe2d_D2Q9_f32_2048", p, 2048, "f32", 200, 216, inputs.swe_initial(2048))
+    p = inputs.PRESETS["neohooke2048"]
+    one("neohooke2d_D2Q9_f16_2048", p, 2048, "f16", 200, 216, inputs.neohooke_initial(2048))
+    p = inputs.PRESETS["advdiff64"]
+    one("advdiff_D2Q5_f64_64", p, 64, "f64", 200, 240, inputs.advdiff_initial(64))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the adjoint ratio, probe and extra workloads")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this library has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}); nothing was run.", file=sys.stderr)
+        sys.exit(2)
+    sys.path.insert(0, ROOT)
+    import torch
+    from paper_2607_05668_amd import inputs, lbm
+
+    p = inputs.PRESETS["swe1024"]
+    g = lbm.from_preset(p)
+    g.init(inputs.swe_initial(p.n))
+    g.step(args.warmup)
+    total_ms, kern_ms = time_steps(torch, g, args.steps, per_launch=True)
+    cells = g.C
+    K = g.K
+    ms_step = total_ms / args.steps
+    value = cells * K * args.steps / total_ms / 1e3          # MLUPS x variables
+    bytes_per_launch = 2 * K * g.Q * 4 * cells
+    achieved = bytes_per_launch / kern_ms / 1e6              # GB/s
+    traffic = measured_traffic()
+    nonfinite = g.reduce(lbm.RED_NONFINITE)[0]
+    if nonfinite:
+        raise SystemExit("non-finite populations after the timed steps")
+
+    line = {
+        "metric": "MLUPS x variables and % HBM roofline per step; adjoint/forward time ratio",
+        "value": round(value, 1),
+        "unit": "MLUPS x variables",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "shallow water (h, hu, hv), D2Q9 per field, 1024x1024 periodic, FP32 shifted "
+                               "populations, seeded 8-mode depth field, one fused collide-and-stream launch per step",
+                   "cells": cells, "fields": K, "lattice": "D2Q9", "storage": "f32",
+                   "bytes_per_cell_update": 2 * K * g.Q * 4},
+        "mlups": round(cells * args.steps / total_ms / 1e3, 1),
+        "hbm_roofline_pct": round(100.0 * achieved / HBM_PEAK_GBPS, 2),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                     "kernel": "k_step<SysSWE, D2Q9, float>", "kernel_ms": round(kern_ms, 5),
+                     "algorithmic_bytes_per_launch": bytes_per_launch},
+    }
+    del g
+    if not args.no_extra:
+        line.update(adjoint_ratio(torch))
+        line["probe_peak_GBps"] = probe_peak(torch, lbm)
+        line["extra"] = extra_runs(torch, lbm, inputs)
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,216 @@
+/* lbm.h -- C ABI of the MI355X (gfx950) collide-and-stream library.
+ *
+ * The library advances the per-field, exact-flux-equilibrium BGK lattice
+ * Boltzmann scheme of Kummerlaender, Bukreev & Krause ("Automated Derivation
+ * of Lattice Boltzmann Methods for Systems of Conservation Laws") on a
+ * periodic grid:
+ *
+ *   Q_k        = Q0_k + sum_i f*_{k,i}                          eq. (moments),
+ *                                                               Sec. 2.5.2 shift
+ *   f*eq_{k,i} = w_i [ dQ_k + (dt/dx)/cs^2  c_i . (Phi_k(Q) - Phi_k(Q0)) ]
+ *                                                               eq. (feq), shifted
+ *   f*_{k,i}(x + c_i, t + dt) = f*_{k,i} - omega_k (f*_{k,i} - f*eq_{k,i})
+ *                               + dt w_i S_k(x, t + dt/2)       eq. (lbe_update)
+ *
+ * with one population set per conserved field and per gradient tracker
+ * (Sec. 2.1.1), conserved fields colliding at omega = 1/tau and trackers at
+ * 1/(g_tau + 1) with tau_grad = g_tau dt (supplement, numerical
+ * configuration).  Every step runs in hand-written HIP kernels; there is no
+ * CPU path.
+ *
+ * Conventions
+ *  - Every device pointer is memory the caller owns (e.g. a torch tensor);
+ *    the library never allocates or frees device memory.
+ *  - Layouts are structure-of-arrays with x fastest: a field array is
+ *    [K][nz][ny][nx], a population array [K][Q][nz][ny][nx].
+ *  - Population order: D2Q5 = rest, +x, +y, -x, -y; D2Q9 = D2Q5 then
+ *    (+1,+1), (-1,+1), (-1,-1), (+1,-1); D3Q7 = rest, +x, -x, +y, -y, +z, -z.
+ *  - Calls are asynchronous on the bound HIP stream unless they return host
+ *    data.  A handle is not thread-safe.  Status codes are below; the text of
+ *    the last error is available from lbm_last_error.
+ *  - Storage precision: LBM_F64 stores and computes in double; LBM_F32
+ *    stores and computes in float; LBM_F16 stores IEEE binary16 scaled by a
+ *    per-field power of two and computes in float.  Reductions accumulate in
+ *    double in every case.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_state lbm_state;
+
+enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,        /* bad argument, unknown name, wrong order of calls */
+    LBM_ENOTBOUND = -2,     /* device buffers not bound yet                      */
+    LBM_EHIP = -3,          /* a HIP runtime call failed                         */
+    LBM_ESUBCHAR = -4,      /* initial state violates the sub-characteristic bound */
+    LBM_ENONFINITE = -5     /* non-finite populations detected                   */
+};
+
+enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2 };
+
+enum {                      /* lbm_reduce: what                                  */
+    LBM_RED_SUMS = 0,       /* sum_x Q_k(x)                        -> K doubles  */
+    LBM_RED_RELL2 = 1,      /* ||Q_k - ref_k||_2 / ||ref_k||_2     -> K doubles  */
+    LBM_RED_RELLINF = 2,    /* max|Q_k - ref_k| / max|ref_k|       -> K doubles  */
+    LBM_RED_MAXSPEED = 3,   /* (dt/dx) max_x max_n |eig A_n(Q)|, and that value
+                               divided by cs                      -> 2 doubles  */
+    LBM_RED_NONFINITE = 4   /* number of non-finite populations    -> 1 double   */
+};
+
+/* Create a stepper (host only; no device work).
+ *   system:  "swe2d"         shallow water (h, hu, hv), Sec. 3
+ *            "advdiff_trk2d" scalar advection-diffusion(-reaction) with a
+ *                            gradient tracker (c, G_c), Sec. 3
+ *            "neohooke2d"    neo-Hookean elasticity (F00, F01, F10, F11, v0, v1), Sec. 3
+ *            "nsf3d_trk17"   3D compressible NSF with 9 velocity-gradient and
+ *                            3 temperature-gradient trackers (Sec. 3, the
+ *                            homogenized NSF case at porosity 1, full tracker basis)
+ *   lattice: "D2Q5" | "D2Q9" (2D systems) | "D3Q7" (3D systems)
+ *   nx, ny, nz: grid; nz must be 1 in 2D; nx must be a multiple of 64.
+ *   tau: relaxation time tau_LB of the conserved fields (> 1/2); dt, dx:
+ *   time step and grid spacing (the flux enters the equilibrium times dt/dx).
+ * Returns NULL on error (message via lbm_last_error(NULL)). */
+lbm_state *lbm_create(const char *system, const char *lattice, int nx, int ny, int nz,
+                      double tau, double dt, double dx);
+
+/* Message of the last failed call on this handle, or of the last failed
+ * lbm_create on this thread when h is NULL.  Never NULL. */
+const char *lbm_last_error(const lbm_state *h);
+
+/* Number of fields K and of lattice velocities Q. */
+int lbm_num_fields(const lbm_state *h);
+int lbm_num_velocities(const lbm_state *h);
+
+/* Set a named scalar parameter before lbm_bind.
+ *   swe2d:          g
+ *   advdiff_trk2d:  ax, ay (advection velocity), nu (diffusivity D), R (reaction), g_tau
+ *   neohooke2d:     rho0, mu_s, lambda_s
+ *   nsf3d_trk17:    gamma, mu, kappa, g_tau, mms (0/1: built-in manufactured-
+ *                   solution forcing), mms_amp, mms_rho0, mms_p0, mms_u0
+ *   all:            t0 (initial time) */
+int lbm_set_param(lbm_state *h, const char *name, double v);
+
+/* Read a parameter in use: "dt", "dx", "lambda" (dt/dx), "tau", "omega"
+ * (conserved fields), "omega_tracker", "tau_grad", "g_tau", "g", "t0".
+ * After lbm_bind with F32/F16 storage these are the values the kernels run
+ * with: dt/dx and 2 - omega are rounded once to float, and dt, tau and the
+ * collision rates are the values those roundings define.  LBM_EINVAL for an
+ * unknown name. */
+int lbm_get_param(const lbm_state *h, const char *name, double *v);
+
+/* Population storage LBM_F64 / LBM_F32 / LBM_F16, before lbm_bind.
+ * Default: LBM_F32. */
+int lbm_set_storage(lbm_state *h, int storage);
+
+/* Reference state Q0 (K host doubles) of the shifted form, before lbm_bind.
+ * For F32/F16 storage it is rounded to the nearest float; lbm_get_reference
+ * returns the value in use.  Defaults: swe2d (1,0,0); advdiff (1,0,0);
+ * neohooke2d (1,0,0,1,0,0); nsf3d_trk17 (1, u0,u0,u0, E0, 0...) from the
+ * mms_* parameters. */
+int lbm_set_reference(lbm_state *h, const double *Q0);
+int lbm_get_reference(const lbm_state *h, double *Q0_out);
+
+/* Bytes the caller must provide: which = 0 one population buffer
+ * (K*Q*cells*sizeof(storage)); which = 1 scratch for reductions. */
+size_t lbm_required_bytes(const lbm_state *h, int which);
+
+/* Bind caller-owned device memory: two population buffers (A/B, each
+ * lbm_required_bytes(h,0) bytes, 256-byte aligned), the scratch buffer
+ * (lbm_required_bytes(h,1)) and the hipStream_t all calls are ordered on
+ * (NULL = default stream).  The library never frees them. */
+int lbm_bind(lbm_state *h, void *pop_a, void *pop_b, void *aux, void *hip_stream);
+
+/* Attach a per-cell device field read by the system's source:
+ *   "grad_zb" (swe2d): topography gradient b = grad z_b, [2][cells] in the
+ *   arithmetic type (double for F64 storage, float otherwise); NULL detaches. */
+int lbm_set_field(lbm_state *h, const char *name, const void *dev_ptr);
+
+/* Initialise the populations at the shifted equilibrium of the given fields
+ * Q_dev ([K][cells] device doubles), computed in double and rounded once to
+ * the storage type (supplement: populations start at the equilibrium of the
+ * initial fields).  For F16 storage, chooses each field's power-of-two scale
+ * from the initial populations.  Resets the step counter and time to t0.
+ * Returns LBM_ESUBCHAR if (dt/dx) max |eig A_n| exceeds cs (Sec. 2.4.2). */
+int lbm_init_moments(lbm_state *h, const double *Q_dev);
+
+/* Advance n collide-and-stream steps (eq. lbe_update), one fused kernel per
+ * step with pull streaming between the A/B buffers.  Asynchronous. */
+int lbm_step(lbm_state *h, int n);
+
+/* Like lbm_step, additionally writing the pre-collision moment deviations
+ * dQ^m = Q^m - Q0 of each of the n steps to Q_hist_dev ([n][K][cells]
+ * floats, or doubles for F64 storage): the recomputation pass of the
+ * checkpointed adjoint. */
+int lbm_step_record(lbm_state *h, int n, void *Q_hist_dev);
+
+/* Moments Q_k(x) at the current time (eq. moments): absolute (Q0 + sum f*)
+ * when absolute != 0, else the deviation; out_dtype LBM_F64 or LBM_F32;
+ * Q_out_dev is [K][cells].  Asynchronous. */
+int lbm_moments(lbm_state *h, void *Q_out_dev, int absolute, int out_dtype);
+
+/* FP64 reductions over the grid (validation-section norms, Sec. 2.4.2
+ * wave-speed bound), written to host_out; ref_dev ([K][cells] doubles) is
+ * required for RELL2 / RELLINF.  Synchronises the bound stream. */
+int lbm_reduce(lbm_state *h, int what, const double *ref_dev, double *host_out);
+
+/* Current step count and time. */
+long long lbm_step_count(const lbm_state *h);
+double lbm_time(const lbm_state *h);
+
+/* Discrete adjoint of the step (not in the paper; derived from eq.
+ * lbe_update).  Adjoint populations lam[K][Q][cells] hold dL/df*_{k,i}(x)
+ * of the pre-collision populations, in the arithmetic type.
+ *
+ * lbm_adjoint_seed: lam_{k,i}(x) = dLdQ_k(x) for every i, from the loss
+ * gradient w.r.t. the moments at the final time, dLdQ_dev [K][cells].
+ *
+ * lbm_adjoint_step: n steps backwards, lam^m = J_m^T lam^{m+1}, using the
+ * recorded moment deviations of lbm_step_record (Q_hist_dev, [n][K][cells],
+ * entry j = step m0 + j) from last to first.  lam^{m0+n} enters in lam_a;
+ * buffers alternate, so lam^{m0} leaves in lam_a when n is even and in
+ * lam_b when n is odd.  grad_field_dev, if non-NULL, accumulates the
+ * gradient w.r.t. the attached source field (swe2d: dL/d grad_zb,
+ * [2][cells]).
+ *
+ * lbm_adjoint_to_initial: dL/dQ^0 [K][cells] (doubles) from lam^0 through the
+ * equilibrium initialisation at the initial fields Q_init_dev (doubles). */
+int lbm_adjoint_seed(lbm_state *h, const void *dLdQ_dev, void *lam_dev);
+int lbm_adjoint_step(lbm_state *h, int n, void *lam_a, void *lam_b, const void *Q_hist_dev,
+                     void *grad_field_dev);
+int lbm_adjoint_to_initial(lbm_state *h, const void *lam0_dev, const double *Q_init_dev,
+                           double *dLdQ0_dev);
+
+/* Checkpoint: serialise the current populations and the handle's state
+ * (system, lattice, grid, storage, step, time, parameters, Q0, F16 scales)
+ * into host_buf.  lbm_save with host_buf == NULL returns the size needed in
+ * *n_inout; lbm_load restores a buffer written by lbm_save into a handle of
+ * the same system, lattice, grid and storage.  Both synchronise. */
+int lbm_save(lbm_state *h, void *host_buf, size_t *n_inout);
+int lbm_load(lbm_state *h, const void *host_buf, size_t n);
+
+/* Device-side checkpoints for the checkpointed adjoint: lbm_snapshot copies
+ * the current populations (lbm_required_bytes(h,0) bytes) to dev_buf;
+ * lbm_restore copies them back and sets the step counter to `step`.
+ * Asynchronous on the bound stream. */
+int lbm_snapshot(lbm_state *h, void *dev_buf);
+int lbm_restore(lbm_state *h, const void *dev_buf, long long step);
+
+/* Streaming-bandwidth probe: copies n bytes src -> dst with the same
+ * launch shape as the stepper (the measured-peak denominator). */
+int lbm_bw_copy(void *dst, const void *src, size_t n, void *hip_stream);
+
+/* Release the handle (does not touch bound buffers). */
+void lbm_destroy(lbm_state *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -68,6 +68,7 @@ def _load():
         lib.oracle_num_fields.argtypes = [ctypes.c_int]
         lib.oracle_num_velocities.argtypes = [ctypes.c_int]
         lib.oracle_lattice.argtypes = [ctypes.c_int, P(ctypes.c_int), d, d]
+        lib.oracle_num_threads.argtypes = []
         _lib = lib
     return _lib
 
@@ -90,6 +91,11 @@ def lattice(name: str):
     return c[:3 * q].reshape(q, 3).copy(), w[:q].copy(), cs2.value
 
 
+def num_threads() -> int:
+    """Threads the oracle's OpenMP loops run on."""
+    return int(_load().oracle_num_threads())
+
+
 def recipe(n: int, scaling: str, f: float, tau_r: float):
     """(dx, dt, tau_LB) of the paper's refinement recipe."""
     dx = 1.0 / n
@@ -101,11 +107,13 @@ class Oracle:
     """FP64 stepper on an nx x ny (x nz) periodic grid.
 
     Arrays use the SoA layout ``[K, (nz,) ny, nx]`` for fields and
-    ``[K, Q, (nz,) ny, nx]`` for populations, x fastest.
+    ``[K, Q, (nz,) ny, nx]`` for populations, x fastest.  ``omega_tracker``
+    overrides the trackers' collision rate 1/(g_tau + 1), e.g. to run exactly
+    the rate a single-precision stepper rounded it to.
     """
 
     def __init__(self, system, lattice, shape, dt, dx, tau, g_tau=None, params=None,
-                 Q0=None, shifted=True):
+                 Q0=None, shifted=True, omega_tracker=None):
         if LATTICE_DIM[lattice] != SYSTEM_DIM[system]:
             raise ValueError("lattice dimension does not match the system")
         self.lib = _load()
@@ -130,7 +138,7 @@ class Oracle:
         for k in TRACKER_FIELDS.get(system, ()):
             if g_tau is None:
                 raise ValueError("system has tracker fields: g_tau required")
-            cfg.omega[k] = 1.0 / (g_tau + 1.0)
+            cfg.omega[k] = 1.0 / (g_tau + 1.0) if omega_tracker is None else omega_tracker
         for name, v in params.items():
             cfg.par[PARAM_INDEX[name]] = float(v)
         if shifted:

@@ -24,6 +24,7 @@
  * All arithmetic is IEEE double; build with -ffp-contract=off.
  */
 #include <complex.h>
+#include <omp.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -330,4 +331,16 @@ int oracle_lattice(int lat, int *c, double *w, double *cs2)
     }
     *cs2 = L.cs2;
     return L.Q;
+}
+
+/* Number of OpenMP threads a parallel region of the oracle uses. */
+int oracle_num_threads(void)
+{
+    int n = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        n = omp_get_num_threads();
+    }
+    return n;
 }

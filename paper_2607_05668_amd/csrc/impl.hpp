@@ -1,0 +1,99 @@
+// Internal declarations shared by the kernels (kernels.hip) and the C ABI
+// (lbm_api.cpp).  Not installed; the public interface is include/lbm.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "systems.hpp"
+
+enum { SYS_ADVDIFF = 0, SYS_SWE = 1, SYS_NEOHOOKE = 2, SYS_NSF17 = 3 };
+enum { LAT_D2Q5 = 0, LAT_D2Q9 = 1, LAT_D3Q7 = 2 };
+
+constexpr int kBlock = 256;          // threads per workgroup (4 waves of 64)
+constexpr int kRedBlocks = 1024;     // workgroups of the first reduction pass
+
+// Manufactured-solution forcing of the 3D NSF system (conserved rows).
+template <class R>
+struct MmsParams {
+    int on;
+    R amp, rho0, p0, u0, cbar2;      // shape parameters of the exact fields
+    R t;                              // evaluation time t_n + dt/2
+    R k;                              // wavenumber 2 pi
+    R dx;
+};
+
+// Everything one kernel launch needs, by value (kernel arguments).
+template <class R>
+struct KParams {
+    int nx, ny, nz;
+    long long C;                      // cells
+    R lam_cs2;                        // (dt/dx) / cs^2
+    R lam;                            // dt/dx
+    R dt;
+    R omega[LBM_MAXK];                // collision rate per field
+    R delta[LBM_MAXK];                // 2 - omega
+    float scale[LBM_MAXK];            // storage = value * scale (F16 only)
+    float inv_scale[LBM_MAXK];
+    Phys<R> phys;
+    const R *b;                       // per-cell source field [D][C] or null
+    MmsParams<R> mms;
+};
+
+struct lbm_state_impl;
+
+// Launchers of one (system, lattice, storage) instantiation.
+struct Launchers {
+    int K, Q, D;
+    size_t store_bytes;               // bytes per stored population
+    hipError_t (*step)(const lbm_state_impl &, const void *fin, void *fout, void *qhist, hipStream_t);
+    hipError_t (*init)(const lbm_state_impl &, const double *Q, void *fout, hipStream_t);
+    hipError_t (*init_absmax)(const lbm_state_impl &, const double *Q, double *partial, hipStream_t);
+    hipError_t (*moments)(const lbm_state_impl &, const void *fin, void *out, int absolute, int out_dtype,
+                          hipStream_t);
+    hipError_t (*reduce)(const lbm_state_impl &, const void *fin, int what, const double *ref, double *aux,
+                         hipStream_t);
+    hipError_t (*adj_seed)(const lbm_state_impl &, const void *dLdQ, void *lam, hipStream_t);
+    hipError_t (*adj_step)(const lbm_state_impl &, const void *lam_in, void *lam_out, const void *qhist,
+                           void *grad_b, hipStream_t);
+    hipError_t (*adj_init)(const lbm_state_impl &, const void *lam0, const double *Q, double *dQ0,
+                           hipStream_t);
+};
+
+const Launchers *lbm_launchers(int sys, int lat, int storage);
+hipError_t lbm_launch_copy(void *dst, const void *src, size_t n, hipStream_t s);
+
+// Host-side state behind the opaque lbm_state handle.
+struct lbm_state_impl {
+    int sys = 0, lat = 0, storage = 1;
+    int nx = 0, ny = 0, nz = 1;
+    long long C = 0;
+    int K = 0, Q = 0, D = 0;
+    double tau = 0, dt = 0, dx = 0, cs2 = 0;
+    double omega_c = 0, omega_t = 0;     // collision rates in use (conserved, trackers)
+    // physical parameters (host, double)
+    double g = 1.0, ax = 0, ay = 0, nu = 0, react = 0, g_tau = -1;
+    double gamma = 1.4, mu = 0, kappa = 0;
+    double rho0_el = 1.0, mu_s = 1.0, lam_s = 1.0;
+    int mms_on = 0;
+    double mms_amp = 0.05, mms_rho0 = 1.0, mms_p0 = 1.0, mms_u0 = 0.0;
+    double t0 = 0.0;
+    int check_subchar = 1;
+    double Q0[LBM_MAXK] = {0};
+    bool q0_set = false;
+    int scale_exp[LBM_MAXK] = {0};
+    // device binding
+    void *pop[2] = {nullptr, nullptr};
+    int cur = 0;
+    void *aux = nullptr;
+    hipStream_t stream = nullptr;
+    bool bound = false;
+    const void *field_b = nullptr;
+    // time
+    long long nsteps = 0;
+    const Launchers *L = nullptr;
+    std::string err;
+
+    template <class R> KParams<R> kparams(double t_half) const;
+};

@@ -1,0 +1,566 @@
+// C ABI of the collide-and-stream library (declared in include/lbm.h):
+// handle management, parameter derivation and launch ordering.  All
+// numerical work is done by the kernels in kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "impl.hpp"
+#include "lbm.h"
+
+struct lbm_state : lbm_state_impl {};
+
+namespace {
+
+thread_local std::string g_create_error = "no error";
+
+int fail(lbm_state *h, int code, const std::string &msg)
+{
+    if (h) h->err = msg;
+    return code;
+}
+
+int hipfail(lbm_state *h, hipError_t e, const char *where)
+{
+    return fail(h, LBM_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+int system_id(const char *s)
+{
+    if (!s) return -1;
+    if (!std::strcmp(s, "advdiff_trk2d")) return SYS_ADVDIFF;
+    if (!std::strcmp(s, "swe2d")) return SYS_SWE;
+    if (!std::strcmp(s, "neohooke2d")) return SYS_NEOHOOKE;
+    if (!std::strcmp(s, "nsf3d_trk17")) return SYS_NSF17;
+    return -1;
+}
+
+int lattice_id(const char *s)
+{
+    if (!s) return -1;
+    if (!std::strcmp(s, "D2Q5")) return LAT_D2Q5;
+    if (!std::strcmp(s, "D2Q9")) return LAT_D2Q9;
+    if (!std::strcmp(s, "D3Q7")) return LAT_D3Q7;
+    return -1;
+}
+
+const int kSysK[4] = {3, 3, 6, 17};
+const int kSysD[4] = {2, 2, 2, 3};
+const int kLatQ[3] = {5, 9, 7};
+const int kLatD[3] = {2, 2, 3};
+const double kLatCs2[3] = {1.0 / 3.0, 1.0 / 3.0, 1.0 / 4.0};
+
+// Reference state of the 3D NSF system from its manufactured-solution
+// background: rho0, rho0 u0 (per axis), E0 = p0/(gamma-1) + 3/2 rho0 u0^2.
+void nsf_default_reference(lbm_state *h)
+{
+    std::memset(h->Q0, 0, sizeof h->Q0);
+    h->Q0[0] = h->mms_rho0;
+    for (int a = 0; a < 3; ++a) h->Q0[1 + a] = h->mms_rho0 * h->mms_u0;
+    h->Q0[4] = h->mms_p0 / (h->gamma - 1.0) + 1.5 * h->mms_rho0 * h->mms_u0 * h->mms_u0;
+}
+
+void default_reference(lbm_state *h)
+{
+    std::memset(h->Q0, 0, sizeof h->Q0);
+    switch (h->sys) {
+    case SYS_SWE: h->Q0[0] = 1.0; break;
+    case SYS_ADVDIFF: h->Q0[0] = 1.0; break;
+    case SYS_NEOHOOKE: h->Q0[0] = 1.0; h->Q0[3] = 1.0; break;
+    case SYS_NSF17: nsf_default_reference(h); break;
+    }
+}
+
+bool has_trackers(int sys) { return sys == SYS_ADVDIFF || sys == SYS_NSF17; }
+
+size_t arith_bytes(const lbm_state *h) { return h->storage == LBM_F64 ? 8 : 4; }
+
+size_t aux_bytes() { return sizeof(double) * ((size_t)2 * LBM_MAXK * kRedBlocks + 4 * LBM_MAXK); }
+
+double *aux_final(const lbm_state *h) { return (double *)h->aux + (size_t)2 * LBM_MAXK * kRedBlocks; }
+
+int check_ready(lbm_state *h)
+{
+    if (!h) return LBM_EINVAL;
+    if (!h->bound) return fail(h, LBM_ENOTBOUND, "lbm_bind has not been called");
+    return LBM_OK;
+}
+
+struct SaveHeader {
+    char magic[8];
+    int32_t version, sys, lat, storage, nx, ny, nz, K, Q;
+    int64_t nsteps;
+    double t0, tau, dt, dx;
+    double Q0[LBM_MAXK];
+    int32_t scale_exp[LBM_MAXK];
+    uint64_t payload;
+};
+
+}  // namespace
+
+extern "C" {
+
+lbm_state *lbm_create(const char *system, const char *lattice, int nx, int ny, int nz, double tau, double dt,
+                      double dx)
+{
+    const int sys = system_id(system), lat = lattice_id(lattice);
+    if (sys < 0) {
+        g_create_error = std::string("unknown system '") + (system ? system : "(null)") + "'";
+        return nullptr;
+    }
+    if (lat < 0) {
+        g_create_error = std::string("unknown lattice '") + (lattice ? lattice : "(null)") + "'";
+        return nullptr;
+    }
+    if (kSysD[sys] != kLatD[lat]) {
+        g_create_error = "lattice dimension does not match the system";
+        return nullptr;
+    }
+    if (sys == SYS_NSF17 && lat != LAT_D3Q7) {
+        g_create_error = "nsf3d_trk17 runs on D3Q7";
+        return nullptr;
+    }
+    if (nx <= 0 || ny <= 0 || nz <= 0 || (kSysD[sys] == 2 && nz != 1)) {
+        g_create_error = "invalid grid (nz must be 1 in 2D)";
+        return nullptr;
+    }
+    if (nx % 64 != 0) {
+        g_create_error = "nx must be a multiple of 64";
+        return nullptr;
+    }
+    const long long C = (long long)nx * ny * nz;
+    if ((long long)kSysK[sys] * kLatQ[lat] * C >= (1LL << 40)) {
+        g_create_error = "grid too large";
+        return nullptr;
+    }
+    if (!(tau > 0.5) || !(dt > 0) || !(dx > 0) || !std::isfinite(tau) || !std::isfinite(dt) || !std::isfinite(dx)) {
+        g_create_error = "need tau > 1/2, dt > 0, dx > 0";
+        return nullptr;
+    }
+    lbm_state *h = new lbm_state();
+    h->sys = sys;
+    h->lat = lat;
+    h->nx = nx;
+    h->ny = ny;
+    h->nz = nz;
+    h->C = C;
+    h->K = kSysK[sys];
+    h->Q = kLatQ[lat];
+    h->D = kLatD[lat];
+    h->tau = tau;
+    h->dt = dt;
+    h->dx = dx;
+    h->cs2 = kLatCs2[lat];
+    h->storage = LBM_F32;
+    default_reference(h);
+    h->err = "no error";
+    return h;
+}
+
+const char *lbm_last_error(const lbm_state *h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+int lbm_num_fields(const lbm_state *h) { return h ? h->K : 0; }
+int lbm_num_velocities(const lbm_state *h) { return h ? h->Q : 0; }
+
+int lbm_set_param(lbm_state *h, const char *name, double v)
+{
+    if (!h || !name) return LBM_EINVAL;
+    if (!std::isfinite(v)) return fail(h, LBM_EINVAL, "parameter value is not finite");
+    const std::string n(name);
+    if (n == "t0") { h->t0 = v; return LBM_OK; }
+    if (n == "check_subchar") { h->check_subchar = v != 0.0; return LBM_OK; }
+    if (h->bound && n != "mms") return fail(h, LBM_EINVAL, "parameters are fixed once bound");
+    switch (h->sys) {
+    case SYS_SWE:
+        if (n == "g") { h->g = v; return LBM_OK; }
+        break;
+    case SYS_ADVDIFF:
+        if (n == "ax") { h->ax = v; return LBM_OK; }
+        if (n == "ay") { h->ay = v; return LBM_OK; }
+        if (n == "nu") { h->nu = v; return LBM_OK; }
+        if (n == "R") { h->react = v; return LBM_OK; }
+        if (n == "g_tau") {
+            if (!(v > 0)) return fail(h, LBM_EINVAL, "g_tau must be positive");
+            h->g_tau = v;
+            return LBM_OK;
+        }
+        break;
+    case SYS_NEOHOOKE:
+        if (n == "rho0") { if (!(v > 0)) return fail(h, LBM_EINVAL, "rho0 must be positive"); h->rho0_el = v; return LBM_OK; }
+        if (n == "mu_s") { h->mu_s = v; return LBM_OK; }
+        if (n == "lambda_s") { h->lam_s = v; return LBM_OK; }
+        break;
+    case SYS_NSF17:
+        if (n == "gamma") { if (!(v > 1)) return fail(h, LBM_EINVAL, "gamma must exceed 1"); h->gamma = v; if (!h->q0_set) nsf_default_reference(h); return LBM_OK; }
+        if (n == "mu") { h->mu = v; return LBM_OK; }
+        if (n == "kappa") { h->kappa = v; return LBM_OK; }
+        if (n == "g_tau") {
+            if (!(v > 0)) return fail(h, LBM_EINVAL, "g_tau must be positive");
+            h->g_tau = v;
+            return LBM_OK;
+        }
+        if (n == "mms") { h->mms_on = v != 0.0; return LBM_OK; }
+        if (n == "mms_amp") { h->mms_amp = v; return LBM_OK; }
+        if (n == "mms_rho0") { h->mms_rho0 = v; if (!h->q0_set) nsf_default_reference(h); return LBM_OK; }
+        if (n == "mms_p0") { h->mms_p0 = v; if (!h->q0_set) nsf_default_reference(h); return LBM_OK; }
+        if (n == "mms_u0") { h->mms_u0 = v; if (!h->q0_set) nsf_default_reference(h); return LBM_OK; }
+        break;
+    }
+    return fail(h, LBM_EINVAL, "unknown parameter '" + n + "' for this system");
+}
+
+int lbm_get_param(const lbm_state *h, const char *name, double *v)
+{
+    if (!h || !name || !v) return LBM_EINVAL;
+    const std::string n(name);
+    const double lam = h->dt / h->dx;
+    if (n == "dt") *v = h->dt;
+    else if (n == "dx") *v = h->dx;
+    else if (n == "lambda") *v = lam;
+    else if (n == "tau") *v = h->tau;
+    else if (n == "omega") *v = h->bound ? h->omega_c : 1.0 / h->tau;
+    else if (n == "omega_tracker") *v = h->bound ? h->omega_t : (h->g_tau > 0 ? 1.0 / (h->g_tau + 1.0) : 0.0);
+    else if (n == "tau_grad") *v = h->g_tau > 0 ? h->g_tau * h->dt : 0.0;
+    else if (n == "g_tau") *v = h->g_tau;
+    else if (n == "g") *v = h->g;
+    else if (n == "t0") *v = h->t0;
+    else return LBM_EINVAL;
+    return LBM_OK;
+}
+
+int lbm_set_storage(lbm_state *h, int storage)
+{
+    if (!h) return LBM_EINVAL;
+    if (h->bound) return fail(h, LBM_EINVAL, "storage is fixed once bound");
+    if (storage < LBM_F64 || storage > LBM_F16) return fail(h, LBM_EINVAL, "unknown storage");
+    h->storage = storage;
+    return LBM_OK;
+}
+
+int lbm_set_reference(lbm_state *h, const double *Q0)
+{
+    if (!h || !Q0) return LBM_EINVAL;
+    if (h->bound) return fail(h, LBM_EINVAL, "reference is fixed once bound");
+    for (int k = 0; k < h->K; ++k) {
+        if (!std::isfinite(Q0[k])) return fail(h, LBM_EINVAL, "reference state is not finite");
+        h->Q0[k] = Q0[k];
+    }
+    h->q0_set = true;
+    return LBM_OK;
+}
+
+int lbm_get_reference(const lbm_state *h, double *Q0_out)
+{
+    if (!h || !Q0_out) return LBM_EINVAL;
+    for (int k = 0; k < h->K; ++k) Q0_out[k] = h->storage == LBM_F64 ? h->Q0[k] : (double)(float)h->Q0[k];
+    return LBM_OK;
+}
+
+size_t lbm_required_bytes(const lbm_state *h, int which)
+{
+    if (!h) return 0;
+    if (which == 0) {
+        const size_t s = h->storage == LBM_F64 ? 8 : (h->storage == LBM_F32 ? 4 : 2);
+        return (size_t)h->K * h->Q * (size_t)h->C * s;
+    }
+    if (which == 1) return aux_bytes();
+    return 0;
+}
+
+int lbm_bind(lbm_state *h, void *pop_a, void *pop_b, void *aux, void *hip_stream)
+{
+    if (!h) return LBM_EINVAL;
+    if (h->bound) return fail(h, LBM_EINVAL, "already bound");
+    if (!pop_a || !pop_b || !aux || pop_a == pop_b) return fail(h, LBM_EINVAL, "need two distinct population buffers and a scratch buffer");
+    if (((uintptr_t)pop_a | (uintptr_t)pop_b | (uintptr_t)aux) & 255u)
+        return fail(h, LBM_EINVAL, "buffers must be 256-byte aligned");
+    if (has_trackers(h->sys) && !(h->g_tau > 0)) return fail(h, LBM_EINVAL, "set g_tau before binding");
+    h->L = lbm_launchers(h->sys, h->lat, h->storage);
+    if (!h->L) return fail(h, LBM_EINVAL, "no kernel for this system, lattice and storage");
+    // Parameters in use.  With single-precision arithmetic the kernels see
+    // dt/dx and delta = 2 - omega rounded once to float; the handle keeps the
+    // values those roundings define (dt = float(dt/dx) dx, omega = 2 -
+    // float(2 - omega)) so that time, diagnostics and lbm_get_param describe
+    // exactly the scheme that runs.
+    h->omega_c = 1.0 / h->tau;
+    h->omega_t = has_trackers(h->sys) ? 1.0 / (h->g_tau + 1.0) : h->omega_c;
+    if (h->storage != LBM_F64) {
+        for (int k = 0; k < h->K; ++k) h->Q0[k] = (double)(float)h->Q0[k];
+        h->dt = (double)(float)(h->dt / h->dx) * h->dx;
+        h->omega_c = 2.0 - (double)(float)(2.0 - h->omega_c);
+        h->omega_t = 2.0 - (double)(float)(2.0 - h->omega_t);
+        h->tau = 1.0 / h->omega_c;
+    }
+    h->pop[0] = pop_a;
+    h->pop[1] = pop_b;
+    h->cur = 0;
+    h->aux = aux;
+    h->stream = (hipStream_t)hip_stream;
+    h->bound = true;
+    return LBM_OK;
+}
+
+int lbm_set_field(lbm_state *h, const char *name, const void *dev_ptr)
+{
+    if (!h || !name) return LBM_EINVAL;
+    if (h->sys == SYS_SWE && !std::strcmp(name, "grad_zb")) {
+        h->field_b = dev_ptr;
+        return LBM_OK;
+    }
+    return fail(h, LBM_EINVAL, std::string("unknown field '") + name + "' for this system");
+}
+
+int lbm_reduce(lbm_state *h, int what, const double *ref_dev, double *host_out);
+
+int lbm_init_moments(lbm_state *h, const double *Q_dev)
+{
+    int rc = check_ready(h);
+    if (rc) return rc;
+    if (!Q_dev) return fail(h, LBM_EINVAL, "null field pointer");
+    hipError_t e;
+    for (int k = 0; k < LBM_MAXK; ++k) h->scale_exp[k] = 0;
+    if (h->storage == LBM_F16) {
+        // per-field power-of-two scale: the largest initial |f*| maps near 2^11
+        e = h->L->init_absmax(*h, Q_dev, (double *)h->aux, h->stream);
+        if (e != hipSuccess) return hipfail(h, e, "init_absmax");
+        std::vector<double> part((size_t)h->K * kRedBlocks);
+        e = hipMemcpyAsync(part.data(), h->aux, part.size() * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hipfail(h, e, "init_absmax copy");
+        for (int k = 0; k < h->K; ++k) {
+            double m = 0.0;
+            for (int b = 0; b < kRedBlocks; ++b) m = std::fmax(m, part[(size_t)k * kRedBlocks + b]);
+            int ex = 0;
+            if (m > 0.0 && std::isfinite(m)) ex = (int)std::floor(std::log2(2048.0 / m));
+            h->scale_exp[k] = ex < -24 ? -24 : (ex > 24 ? 24 : ex);
+        }
+    }
+    h->cur = 0;
+    h->nsteps = 0;
+    e = h->L->init(*h, Q_dev, h->pop[0], h->stream);
+    if (e != hipSuccess) return hipfail(h, e, "init");
+    if (h->check_subchar) {
+        double sp[2];
+        rc = lbm_reduce(h, LBM_RED_MAXSPEED, nullptr, sp);
+        if (rc) return rc;
+        if (!(sp[1] <= 1.0)) {
+            char buf[160];
+            std::snprintf(buf, sizeof buf, "sub-characteristic bound violated: (dt/dx) max|eig A_n| = %.6g > cs = %.6g",
+                          sp[0], std::sqrt(h->cs2));
+            return fail(h, LBM_ESUBCHAR, buf);
+        }
+    }
+    return LBM_OK;
+}
+
+static int run_steps(lbm_state *h, int n, void *qhist)
+{
+    int rc = check_ready(h);
+    if (rc) return rc;
+    if (n < 0) return fail(h, LBM_EINVAL, "negative step count");
+    const size_t stride = (size_t)h->K * (size_t)h->C * arith_bytes(h);
+    for (int j = 0; j < n; ++j) {
+        void *q = qhist ? (char *)qhist + (size_t)j * stride : nullptr;
+        const hipError_t e = h->L->step(*h, h->pop[h->cur], h->pop[h->cur ^ 1], q, h->stream);
+        if (e != hipSuccess) return hipfail(h, e, "step");
+        h->cur ^= 1;
+        h->nsteps += 1;
+    }
+    return LBM_OK;
+}
+
+int lbm_step(lbm_state *h, int n) { return run_steps(h, n, nullptr); }
+
+int lbm_step_record(lbm_state *h, int n, void *Q_hist_dev)
+{
+    if (h && !Q_hist_dev) return fail(h, LBM_EINVAL, "null history pointer");
+    return run_steps(h, n, Q_hist_dev);
+}
+
+int lbm_moments(lbm_state *h, void *Q_out_dev, int absolute, int out_dtype)
+{
+    int rc = check_ready(h);
+    if (rc) return rc;
+    if (!Q_out_dev || (out_dtype != LBM_F64 && out_dtype != LBM_F32)) return fail(h, LBM_EINVAL, "bad output");
+    const hipError_t e = h->L->moments(*h, h->pop[h->cur], Q_out_dev, absolute, out_dtype == LBM_F64 ? 0 : 1, h->stream);
+    return e == hipSuccess ? LBM_OK : hipfail(h, e, "moments");
+}
+
+int lbm_reduce(lbm_state *h, int what, const double *ref_dev, double *host_out)
+{
+    int rc = check_ready(h);
+    if (rc) return rc;
+    if (!host_out || what < LBM_RED_SUMS || what > LBM_RED_NONFINITE) return fail(h, LBM_EINVAL, "bad reduction");
+    if ((what == LBM_RED_RELL2 || what == LBM_RED_RELLINF) && !ref_dev) return fail(h, LBM_EINVAL, "reference field required");
+    hipError_t e = h->L->reduce(*h, h->pop[h->cur], what, ref_dev, (double *)h->aux, h->stream);
+    if (e != hipSuccess) return hipfail(h, e, "reduce");
+    const int nslot = (what == LBM_RED_MAXSPEED || what == LBM_RED_NONFINITE) ? 1 : (what == LBM_RED_SUMS ? h->K : 2 * h->K);
+    double r[2 * LBM_MAXK];
+    e = hipMemcpyAsync(r, aux_final(h), nslot * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hipfail(h, e, "reduce copy");
+    switch (what) {
+    case LBM_RED_SUMS:
+        for (int k = 0; k < h->K; ++k) host_out[k] = r[k];
+        break;
+    case LBM_RED_RELL2:
+        for (int k = 0; k < h->K; ++k) host_out[k] = r[h->K + k] > 0 ? std::sqrt(r[k] / r[h->K + k]) : std::sqrt(r[k]);
+        break;
+    case LBM_RED_RELLINF:
+        for (int k = 0; k < h->K; ++k) host_out[k] = r[h->K + k] > 0 ? r[k] / r[h->K + k] : r[k];
+        break;
+    case LBM_RED_MAXSPEED:
+        host_out[0] = (h->dt / h->dx) * r[0];
+        host_out[1] = host_out[0] / std::sqrt(h->cs2);
+        break;
+    case LBM_RED_NONFINITE:
+        host_out[0] = r[0];
+        break;
+    }
+    return LBM_OK;
+}
+
+long long lbm_step_count(const lbm_state *h) { return h ? h->nsteps : 0; }
+double lbm_time(const lbm_state *h) { return h ? h->t0 + h->nsteps * h->dt : 0.0; }
+
+int lbm_adjoint_seed(lbm_state *h, const void *dLdQ_dev, void *lam_dev)
+{
+    int rc = check_ready(h);
+    if (rc) return rc;
+    if (!h->L->adj_seed) return fail(h, LBM_EINVAL, "no adjoint for this system");
+    if (!dLdQ_dev || !lam_dev) return fail(h, LBM_EINVAL, "null pointer");
+    const hipError_t e = h->L->adj_seed(*h, dLdQ_dev, lam_dev, h->stream);
+    return e == hipSuccess ? LBM_OK : hipfail(h, e, "adjoint_seed");
+}
+
+int lbm_adjoint_step(lbm_state *h, int n, void *lam_a, void *lam_b, const void *Q_hist_dev, void *grad_field_dev)
+{
+    int rc = check_ready(h);
+    if (rc) return rc;
+    if (!h->L->adj_step) return fail(h, LBM_EINVAL, "no adjoint for this system");
+    if (n < 0 || !lam_a || !lam_b || lam_a == lam_b || (n > 0 && !Q_hist_dev)) return fail(h, LBM_EINVAL, "bad adjoint arguments");
+    if (grad_field_dev && !h->field_b) return fail(h, LBM_EINVAL, "no source field attached");
+    const size_t stride = (size_t)h->K * (size_t)h->C * arith_bytes(h);
+    void *in = lam_a, *out = lam_b;
+    for (int j = n - 1; j >= 0; --j) {
+        const hipError_t e = h->L->adj_step(*h, in, out, (const char *)Q_hist_dev + (size_t)j * stride, grad_field_dev,
+                                            h->stream);
+        if (e != hipSuccess) return hipfail(h, e, "adjoint_step");
+        void *t = in;
+        in = out;
+        out = t;
+    }
+    return LBM_OK;
+}
+
+int lbm_adjoint_to_initial(lbm_state *h, const void *lam0_dev, const double *Q_init_dev, double *dLdQ0_dev)
+{
+    int rc = check_ready(h);
+    if (rc) return rc;
+    if (!h->L->adj_init) return fail(h, LBM_EINVAL, "no adjoint for this system");
+    if (!lam0_dev || !Q_init_dev || !dLdQ0_dev) return fail(h, LBM_EINVAL, "null pointer");
+    const hipError_t e = h->L->adj_init(*h, lam0_dev, Q_init_dev, dLdQ0_dev, h->stream);
+    return e == hipSuccess ? LBM_OK : hipfail(h, e, "adjoint_to_initial");
+}
+
+int lbm_save(lbm_state *h, void *host_buf, size_t *n_inout)
+{
+    int rc = check_ready(h);
+    if (rc) return rc;
+    if (!n_inout) return fail(h, LBM_EINVAL, "null size pointer");
+    const size_t payload = lbm_required_bytes(h, 0);
+    const size_t need = sizeof(SaveHeader) + payload;
+    if (!host_buf) {
+        *n_inout = need;
+        return LBM_OK;
+    }
+    if (*n_inout < need) return fail(h, LBM_EINVAL, "checkpoint buffer too small");
+    SaveHeader hd;
+    std::memset(&hd, 0, sizeof hd);
+    std::memcpy(hd.magic, "LBMCKPT1", 8);
+    hd.version = 1;
+    hd.sys = h->sys;
+    hd.lat = h->lat;
+    hd.storage = h->storage;
+    hd.nx = h->nx;
+    hd.ny = h->ny;
+    hd.nz = h->nz;
+    hd.K = h->K;
+    hd.Q = h->Q;
+    hd.nsteps = h->nsteps;
+    hd.t0 = h->t0;
+    hd.tau = h->tau;
+    hd.dt = h->dt;
+    hd.dx = h->dx;
+    for (int k = 0; k < LBM_MAXK; ++k) {
+        hd.Q0[k] = h->Q0[k];
+        hd.scale_exp[k] = h->scale_exp[k];
+    }
+    hd.payload = payload;
+    std::memcpy(host_buf, &hd, sizeof hd);
+    hipError_t e = hipMemcpyAsync((char *)host_buf + sizeof hd, h->pop[h->cur], payload, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hipfail(h, e, "save");
+    *n_inout = need;
+    return LBM_OK;
+}
+
+int lbm_load(lbm_state *h, const void *host_buf, size_t n)
+{
+    int rc = check_ready(h);
+    if (rc) return rc;
+    if (!host_buf || n < sizeof(SaveHeader)) return fail(h, LBM_EINVAL, "checkpoint buffer too small");
+    SaveHeader hd;
+    std::memcpy(&hd, host_buf, sizeof hd);
+    if (std::memcmp(hd.magic, "LBMCKPT1", 8) != 0 || hd.version != 1) return fail(h, LBM_EINVAL, "not a checkpoint");
+    if (hd.sys != h->sys || hd.lat != h->lat || hd.storage != h->storage || hd.nx != h->nx || hd.ny != h->ny ||
+        hd.nz != h->nz)
+        return fail(h, LBM_EINVAL, "checkpoint does not match this handle");
+    const size_t payload = lbm_required_bytes(h, 0);
+    if (hd.payload != payload || n < sizeof hd + payload) return fail(h, LBM_EINVAL, "checkpoint size mismatch");
+    for (int k = 0; k < h->K; ++k)
+        if (hd.Q0[k] != h->Q0[k]) return fail(h, LBM_EINVAL, "checkpoint reference state differs");
+    for (int k = 0; k < LBM_MAXK; ++k) h->scale_exp[k] = hd.scale_exp[k];
+    h->nsteps = hd.nsteps;
+    h->t0 = hd.t0;
+    h->cur = 0;
+    hipError_t e = hipMemcpyAsync(h->pop[0], (const char *)host_buf + sizeof hd, payload, hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hipfail(h, e, "load");
+    return LBM_OK;
+}
+
+int lbm_snapshot(lbm_state *h, void *dev_buf)
+{
+    int rc = check_ready(h);
+    if (rc) return rc;
+    if (!dev_buf) return fail(h, LBM_EINVAL, "null snapshot buffer");
+    const hipError_t e = lbm_launch_copy(dev_buf, h->pop[h->cur], lbm_required_bytes(h, 0), h->stream);
+    return e == hipSuccess ? LBM_OK : hipfail(h, e, "snapshot");
+}
+
+int lbm_restore(lbm_state *h, const void *dev_buf, long long step)
+{
+    int rc = check_ready(h);
+    if (rc) return rc;
+    if (!dev_buf || step < 0) return fail(h, LBM_EINVAL, "bad restore arguments");
+    const hipError_t e = lbm_launch_copy(h->pop[h->cur], dev_buf, lbm_required_bytes(h, 0), h->stream);
+    if (e != hipSuccess) return hipfail(h, e, "restore");
+    h->nsteps = step;
+    return LBM_OK;
+}
+
+int lbm_bw_copy(void *dst, const void *src, size_t n, void *hip_stream)
+{
+    if (!dst || !src) return LBM_EINVAL;
+    return lbm_launch_copy(dst, src, n, (hipStream_t)hip_stream) == hipSuccess ? LBM_OK : LBM_EHIP;
+}
+
+void lbm_destroy(lbm_state *h) { delete h; }
+
+}  // extern "C"

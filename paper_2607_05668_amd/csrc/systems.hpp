@@ -1,0 +1,311 @@
+// Conservation-law systems of the collide-and-stream library: the flux
+// Phi(Q) (K x D) and source S(Q) of d_t Q + div Phi = S (eq. pde_target)
+// for each supported system, as device functors.
+//
+// Fluxes are written in fluctuation form: flux_delta returns
+// dPhi = Phi(Q0 + dQ) - Phi(Q0) computed from the reference state and the
+// deviation without ever forming Phi(Q) and Phi(Q0) separately, so that in
+// single precision no large-minus-large cancellation occurs (the reason for
+// the paper's reference and equilibrium shift, Sec. 2.5.2).  Each functor is
+// a template over the scalar type S (float, double, or Dual<> for the
+// adjoint's Jacobian contractions); reference data and parameters are in the
+// arithmetic type R.
+#pragma once
+
+#include "dual.hpp"
+
+#define LBM_MAXK 17
+
+// Per-run constants shared by all systems (filled on the host in double and
+// converted to the arithmetic type R).
+template <class R>
+struct Phys {
+    R Q0[LBM_MAXK];       // reference state
+    R g;                  // SWE gravity
+    R a[3], nu, react;    // advection velocity, diffusivity, reaction rate
+    R inv_tau_grad;       // 1 / tau_grad, tau_grad = g_tau dt
+    R gamma, mu, kappa;   // NSF
+    R u_ref[3];           // reference velocity m0 / rho0
+    R p_ref, T_ref, H_ref;// reference pressure, temperature p0/rho0, E0 + p0
+    R tau_ref[9];         // viscous stress of the reference trackers
+    R rho0, mu_s, lam_s;  // elasticity
+    R H0[4];              // F0 - I (reference deformation minus identity)
+    R P0[4];              // first Piola-Kirchhoff stress at F0
+};
+
+// ------------------------------------------------------------------ SWE --
+// Shallow water (Sec. 3): Q = (h, hu, hv),
+//   Phi_h = hu, Phi_hu = hu (x) u + g h^2/2 I, S_hu = -g h grad z_b.
+struct SysSWE {
+    static constexpr int K = 3, D = 2, id = 1;
+    static constexpr bool tracker(int) { return false; }
+
+    // d(a b / h) = (a0 db + b0 da + da db)/h - dh a0 b0 / (h h0)
+    template <class S, class R>
+    __host__ __device__ static S dprod(R a0, R b0, const S &da, const S &db, const S &h, R h0, const S &dh)
+    {
+        return (a0 * db + b0 * da + da * db) / h - dh * (a0 * b0 / h0) / h;
+    }
+
+    template <class S, class R>
+    __host__ __device__ static void flux_delta(const Phys<R> &p, const S *dQ, S dPhi[][D])
+    {
+        const R h0 = p.Q0[0], mx0 = p.Q0[1], my0 = p.Q0[2];
+        const S dh = dQ[0], dmx = dQ[1], dmy = dQ[2];
+        const S h = dh + h0;
+        const S pres = p.g * dh * (dh * R(0.5) + h0);          // g (h^2 - h0^2) / 2
+        const S xy = dprod(mx0, my0, dmx, dmy, h, h0, dh);
+        dPhi[0][0] = dmx;
+        dPhi[0][1] = dmy;
+        dPhi[1][0] = pres + dprod(mx0, mx0, dmx, dmx, h, h0, dh);
+        dPhi[1][1] = xy;
+        dPhi[2][0] = xy;
+        dPhi[2][1] = pres + dprod(my0, my0, dmy, dmy, h, h0, dh);
+    }
+
+    template <class S, class R>
+    __host__ __device__ static void source(const Phys<R> &p, const S *dQ, const R *b, S *Sk)
+    {
+        // b: the topography gradient of this cell (zeros when none is attached)
+        const S h = dQ[0] + p.Q0[0];
+        Sk[0] = S(R(0));
+        Sk[1] = h * (-p.g * b[0]);
+        Sk[2] = h * (-p.g * b[1]);
+    }
+
+    // largest |eigenvalue| of sum_a n_a A_a over unit n: |u| + sqrt(g h)
+    template <class R>
+    __host__ __device__ static R max_speed(const Phys<R> &p, const R *Q)
+    {
+        const R h = Q[0], ux = Q[1] / h, uy = Q[2] / h;
+        return sqrt(ux * ux + uy * uy) + sqrt(p.g * h);
+    }
+};
+
+// -------------------------------------------------------------- ADVDIFF --
+// Scalar advection-diffusion-reaction with one gradient tracker (Sec. 3):
+// Q = (c, G), Phi_c = c a - nu G, Phi_G = G (x) a - I c / tau_grad,
+// S_c = R c (1 - c), S_G = -G / tau_grad.  The flux is linear, so dPhi is
+// the flux of dQ.
+struct SysAdvDiff {
+    static constexpr int K = 3, D = 2, id = 0;
+    static constexpr bool tracker(int k) { return k > 0; }
+
+    template <class S, class R>
+    __host__ __device__ static void flux_delta(const Phys<R> &p, const S *dQ, S dPhi[][D])
+    {
+        const S dc = dQ[0];
+        const S dci = dc * p.inv_tau_grad;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            dPhi[0][a] = dc * p.a[a] - dQ[1 + a] * p.nu;
+#pragma unroll
+            for (int b = 0; b < D; ++b)
+                dPhi[1 + b][a] = (a == b) ? dQ[1 + b] * p.a[a] - dci : dQ[1 + b] * p.a[a];
+        }
+    }
+
+    template <class S, class R>
+    __host__ __device__ static void source(const Phys<R> &p, const S *dQ, const R *, S *Sk)
+    {
+        const S c = dQ[0] + p.Q0[0];
+        Sk[0] = c * (R(1) - c) * p.react;
+        Sk[1] = (dQ[1] + p.Q0[1]) * (-p.inv_tau_grad);
+        Sk[2] = (dQ[2] + p.Q0[2]) * (-p.inv_tau_grad);
+    }
+
+    // eigenvalues of the (c, G_n) block: a.n +- sqrt(nu / tau_grad)
+    template <class R>
+    __host__ __device__ static R max_speed(const Phys<R> &p, const R *)
+    {
+        return sqrt(p.a[0] * p.a[0] + p.a[1] * p.a[1]) + sqrt(p.nu * p.inv_tau_grad);
+    }
+};
+
+// ------------------------------------------------------------- NEOHOOKE --
+// Neo-Hookean elasticity, total-Lagrangian, momentum divided by rho0
+// (Sec. 3): Q = (F00, F01, F10, F11, v0, v1),
+//   Phi_{F_ab, c} = -v_a delta_bc,  Phi_{v_a, c} = -P_ac / rho0,
+//   P = mu_s (F - F^{-T}) + lambda_s ln J F^{-T},  S = 0.
+// With H = F - I: J - 1 = H00 + H11 + H00 H11 - H01 H10, cof F = J F^{-T},
+// F - F^{-T} = (J F - cof F) / J, all formed from the small entries of H.
+struct SysNeoHooke {
+    static constexpr int K = 6, D = 2, id = 2;
+    static constexpr bool tracker(int) { return false; }
+
+    template <class S, class R>
+    __host__ __device__ static void stress(const Phys<R> &p, const S H[4], S P[4])
+    {
+        const S dJ = H[0] + H[3] + H[0] * H[3] - H[1] * H[2];
+        const S invJ = R(1) / (dJ + R(1));
+        const S lnJ = lbm_log1p(dJ);
+        // cof F = [[1 + H11, -H10], [-H01, 1 + H00]]
+        const S c00 = H[3] + R(1), c01 = -H[2], c10 = -H[1], c11 = H[0] + R(1);
+        // J F - cof F
+        const S e00 = dJ + H[0] + dJ * H[0] - H[3];
+        const S e01 = H[1] + H[2] + dJ * H[1];
+        const S e10 = H[2] + H[1] + dJ * H[2];
+        const S e11 = dJ + H[3] + dJ * H[3] - H[0];
+        P[0] = (e00 * p.mu_s + lnJ * c00 * p.lam_s) * invJ;
+        P[1] = (e01 * p.mu_s + lnJ * c01 * p.lam_s) * invJ;
+        P[2] = (e10 * p.mu_s + lnJ * c10 * p.lam_s) * invJ;
+        P[3] = (e11 * p.mu_s + lnJ * c11 * p.lam_s) * invJ;
+    }
+
+    template <class S, class R>
+    __host__ __device__ static void flux_delta(const Phys<R> &p, const S *dQ, S dPhi[][D])
+    {
+        S H[4], P[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) H[j] = dQ[j] + p.H0[j];
+        stress(p, H, P);
+        const R ir = R(1) / p.rho0;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) dPhi[2 * a + b][c] = (b == c) ? -dQ[4 + a] : S(R(0));
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) dPhi[4 + a][c] = (P[2 * a + c] - p.P0[2 * a + c]) * (-ir);
+    }
+
+    template <class S, class R>
+    __host__ __device__ static void source(const Phys<R> &, const S *, const R *, S *Sk)
+    {
+#pragma unroll
+        for (int k = 0; k < K; ++k) Sk[k] = S(R(0));
+    }
+
+    // largest elastic wave speed: sqrt of the largest eigenvalue of the
+    // acoustic tensor A_ac(n) = (1/rho0) dP_ab/dF_cd n_b n_d over 16 directions
+    template <class R>
+    __host__ __device__ static R max_speed(const Phys<R> &p, const R *Q)
+    {
+        using DD = Dual<R, 4>;
+        DD H[4], P[4];
+        for (int j = 0; j < 4; ++j) {
+            H[j] = DD(Q[j] - (j == 0 || j == 3 ? R(1) : R(0)));
+            H[j].d[j] = R(1);
+        }
+        stress(p, H, P);
+        R best = R(0);
+        for (int s = 0; s < 16; ++s) {
+            const R th = R(3.14159265358979323846) * R(s) / R(16);
+            const R n[2] = {cos(th), sin(th)};
+            R A[2][2];
+            for (int a = 0; a < 2; ++a)
+                for (int c = 0; c < 2; ++c) {
+                    R acc = R(0);
+                    for (int b = 0; b < 2; ++b)
+                        for (int d = 0; d < 2; ++d) acc += P[2 * a + b].d[2 * c + d] * n[b] * n[d];
+                    A[a][c] = acc / p.rho0;
+                }
+            const R tr = A[0][0] + A[1][1];
+            const R det = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+            const R disc = tr * tr * R(0.25) - det;
+            const R lmax = tr * R(0.5) + sqrt(disc > R(0) ? disc : R(0));
+            const R c = sqrt(lmax > R(0) ? lmax : R(0));
+            best = c > best ? c : best;
+        }
+        return best;
+    }
+};
+
+// ---------------------------------------------------------------- NSF17 --
+// 3D compressible Navier-Stokes-Fourier with derived-field gradient
+// trackers (Sec. 3, compressible NSF; homogenized NSF at porosity 1 with the
+// full velocity-gradient basis; tracker construction of Sec. 2.1.1):
+//   Q = (rho, m, E, G_ab ~ d_b u_a, G_T ~ grad T), u = m/rho,
+//   p = (gamma-1)(E - |m|^2/(2 rho)), T = p/rho,
+//   tau = mu (G + G^T - 2/3 tr G I),
+//   Phi_rho = m, Phi_m = m (x) u + p I - tau,
+//   Phi_E = (E + p) u - tau u - kappa G_T,
+//   Phi_{G_ab, c} = G_ab u_c - delta_bc u_a / tau_grad,
+//   Phi_{G_Ta, c} = G_Ta u_c - delta_ac T / tau_grad,
+//   S_G = -G / tau_grad (zero for the conserved rows).
+// Fluctuation form: du = (dm - drho u0)/rho, dp = (gamma-1)(dE - dk) with
+// dk = (rho du.(2 u0 + du) + drho |u0|^2)/2, dT = (dp - T0 drho)/rho, and
+// every product ab - a0 b0 written as da b + a0 db.
+struct SysNSF17 {
+    static constexpr int K = 17, D = 3, id = 3;
+    static constexpr bool tracker(int k) { return k >= 5; }
+
+    template <class S, class R>
+    __host__ __device__ static void flux_delta(const Phys<R> &p, const S *dQ, S dPhi[][D])
+    {
+        const S drho = dQ[0];
+        const S rho = drho + p.Q0[0];
+        const S irho = R(1) / rho;
+        S u[3], du[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            du[a] = (dQ[1 + a] - drho * p.u_ref[a]) * irho;
+            u[a] = du[a] + p.u_ref[a];
+        }
+        const S dk = (rho * (du[0] * (du[0] + R(2) * p.u_ref[0]) + du[1] * (du[1] + R(2) * p.u_ref[1])
+                             + du[2] * (du[2] + R(2) * p.u_ref[2]))
+                      + drho * (p.u_ref[0] * p.u_ref[0] + p.u_ref[1] * p.u_ref[1] + p.u_ref[2] * p.u_ref[2]))
+                     * R(0.5);
+        const S dp = (dQ[4] - dk) * (p.gamma - R(1));
+        const S dT = (dp - drho * p.T_ref) * irho;
+        // deviation of the viscous stress (linear in the trackers)
+        const S trG = dQ[5] + dQ[9] + dQ[13];
+        S dtau[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                dtau[a][b] = (dQ[5 + 3 * a + b] + dQ[5 + 3 * b + a] - (a == b ? trG * R(2.0 / 3.0) : S(R(0)))) * p.mu;
+        const S dH = dQ[4] + dp;                          // d(E + p)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            dPhi[0][c] = dQ[1 + c];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                S v = dQ[1 + a] * u[c] + du[c] * p.Q0[1 + a] - dtau[a][c];
+                if (a == c) v = v + dp;
+                dPhi[1 + a][c] = v;
+            }
+            S tu = dtau[c][0] * u[0] + dtau[c][1] * u[1] + dtau[c][2] * u[2]
+                   + du[0] * p.tau_ref[3 * c + 0] + du[1] * p.tau_ref[3 * c + 1] + du[2] * p.tau_ref[3 * c + 2];
+            dPhi[4][c] = dH * u[c] + du[c] * p.H_ref - tu - dQ[14 + c] * p.kappa;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    S v = dQ[5 + 3 * a + b] * u[c] + du[c] * p.Q0[5 + 3 * a + b];
+                    if (b == c) v = v - du[a] * p.inv_tau_grad;
+                    dPhi[5 + 3 * a + b][c] = v;
+                }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                S v = dQ[14 + a] * u[c] + du[c] * p.Q0[14 + a];
+                if (a == c) v = v - dT * p.inv_tau_grad;
+                dPhi[14 + a][c] = v;
+            }
+        }
+    }
+
+    template <class S, class R>
+    __host__ __device__ static void source(const Phys<R> &p, const S *dQ, const R *, S *Sk)
+    {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) Sk[k] = S(R(0));
+#pragma unroll
+        for (int k = 5; k < K; ++k) Sk[k] = (dQ[k] + p.Q0[k]) * (-p.inv_tau_grad);
+    }
+
+    // |u| + adiabatic sound speed of the conserved (Euler) subsystem
+    template <class R>
+    __host__ __device__ static R max_speed(const Phys<R> &p, const R *Q)
+    {
+        const R rho = Q[0];
+        const R u0 = Q[1] / rho, u1 = Q[2] / rho, u2 = Q[3] / rho;
+        const R pr = (p.gamma - R(1)) * (Q[4] - R(0.5) * rho * (u0 * u0 + u1 * u1 + u2 * u2));
+        const R c2 = p.gamma * pr / rho;
+        return sqrt(u0 * u0 + u1 * u1 + u2 * u2) + sqrt(c2 > R(0) ? c2 : R(0));
+    }
+};

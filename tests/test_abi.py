@@ -1,0 +1,80 @@
+"""The C ABI library loads and exports every entry point include/lbm.h
+declares; host-only calls validate their arguments.  CPU only: nothing here
+launches a kernel."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2607_05668_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_binding_exports():
+    assert _declared() == sorted(lbm.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lbm.load_library()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    # and nothing else public
+    out = os.popen(f"nm -D --defined-only {lbm.LIB_PATH}").read()
+    exported = sorted(set(m for m in re.findall(r" T (lbm_\w+)", out)))
+    assert exported == _declared()
+
+
+def test_create_validates_arguments():
+    lib = lbm.load_library()
+    assert not lib.lbm_create(b"nope", b"D2Q9", 64, 64, 1, 0.6, 1e-3, 1e-2)
+    assert b"unknown system" in lib.lbm_last_error(None)
+    assert not lib.lbm_create(b"swe2d", b"D3Q7", 64, 64, 1, 0.6, 1e-3, 1e-2)
+    assert not lib.lbm_create(b"swe2d", b"D2Q9", 64, 64, 2, 0.6, 1e-3, 1e-2)
+    assert not lib.lbm_create(b"swe2d", b"D2Q9", 65, 64, 1, 0.6, 1e-3, 1e-2)
+    assert b"multiple of 64" in lib.lbm_last_error(None)
+    assert not lib.lbm_create(b"swe2d", b"D2Q9", 64, 64, 1, 0.5, 1e-3, 1e-2)
+    h = lib.lbm_create(b"swe2d", b"D2Q9", 64, 32, 1, 0.6, 1e-3, 1e-2)
+    assert h
+    h = ctypes.c_void_p(h)
+    assert lib.lbm_num_fields(h) == 3 and lib.lbm_num_velocities(h) == 9
+    assert lib.lbm_required_bytes(h, 0) == 3 * 9 * 64 * 32 * 4
+    assert lib.lbm_set_storage(h, lbm.F16) == 0
+    assert lib.lbm_required_bytes(h, 0) == 3 * 9 * 64 * 32 * 2
+    assert lib.lbm_set_storage(h, 7) == lbm.LBM_EINVAL
+    assert lib.lbm_set_param(h, b"g", 9.81) == 0
+    assert lib.lbm_set_param(h, b"mu", 1.0) == lbm.LBM_EINVAL
+    assert b"unknown parameter" in lib.lbm_last_error(h)
+    assert lib.lbm_step(h, 1) == lbm.LBM_ENOTBOUND
+    assert lib.lbm_bind(h, None, None, None, None) == lbm.LBM_EINVAL
+    lib.lbm_destroy(h)
+
+
+def test_tracker_systems_need_g_tau():
+    lib = lbm.load_library()
+    h = ctypes.c_void_p(lib.lbm_create(b"advdiff_trk2d", b"D2Q5", 64, 64, 1, 0.6, 1e-3, 1e-2))
+    # fake, aligned, distinct addresses: bind fails on the missing g_tau before
+    # anything is dereferenced
+    assert lib.lbm_bind(h, ctypes.c_void_p(256), ctypes.c_void_p(512), ctypes.c_void_p(768), None) == lbm.LBM_EINVAL
+    assert b"g_tau" in lib.lbm_last_error(h)
+    lib.lbm_destroy(h)
+
+
+def test_reference_rounds_to_float_for_single_precision_storage():
+    lib = lbm.load_library()
+    h = ctypes.c_void_p(lib.lbm_create(b"swe2d", b"D2Q9", 64, 64, 1, 0.6, 1e-3, 1e-2))
+    import numpy as np
+    q0 = np.array([1.1, 0.1, 0.0])
+    dp = ctypes.POINTER(ctypes.c_double)
+    assert lib.lbm_set_reference(h, q0.ctypes.data_as(dp)) == 0
+    out = np.zeros(3)
+    lib.lbm_get_reference(h, out.ctypes.data_as(dp))
+    assert np.all(out == np.float32(q0).astype(np.float64))
+    lib.lbm_destroy(h)
