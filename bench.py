@@ -11,8 +11,8 @@ region.
 
 Printed: one JSON line with MLUPS x variables (the metric), the HBM
 roofline of the step kernel (algorithmic 2*K*Q*4 = 216 bytes per cell
-update over the kernel's average duration from HIP events recorded around
-every launch on the stream the kernel runs on), the FP64 CPU oracle on a
+update over the kernel's average launch duration: HIP events on the stream
+the kernel runs on bracket the K back-to-back launches), the FP64 CPU oracle on a
 bounded sample of the same workload, and the adjoint/forward time ratio of
 the checkpointed shallow-water rollout (512^2, 500 steps, snapshot every 50).
 """
@@ -163,6 +163,8 @@ def extra_runs(torch, lbm, inputs):
     one("neohooke2d_D2Q9_f16_2048", p, 2048, "f16", 200, 216, inputs.neohooke_initial(2048))
     p = inputs.PRESETS["advdiff64"]
     one("advdiff_D2Q5_f64_64", p, 64, "f64", 200, 240, inputs.advdiff_initial(64))
+    p = inputs.PRESETS["nsf256"]
+    one("nsf3d_trk17_D3Q7_f32_256_mms", p, 256, "f32", 50, 952, inputs.nsf_exact(256, 0.0))
     return out
 
 
@@ -173,6 +175,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the adjoint ratio, probe and extra workloads")
+    ap.add_argument("--counters", action="store_true", help="short run for rocprofv3 counter collection")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this library has no multi-GPU path "
@@ -186,7 +189,22 @@ def main():
     g = lbm.from_preset(p)
     g.init(inputs.swe_initial(p.n))
     g.step(args.warmup)
-    total_ms, kern_ms = time_steps(torch, g, args.steps, per_launch=True)
+    if args.counters:
+        # counter runs (rocprofv3 --pmc): a short stepping burst, then copies of
+        # a known size whose counter readings scale the stepping kernel's
+        g.step(50)
+        n = 1 << 30
+        a = torch.zeros(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty(n, dtype=torch.uint8, device="cuda")
+        for _ in range(5):
+            lbm.bw_copy(b, a, n)
+        torch.cuda.synchronize()
+        print(json.dumps({"counters_run": True, "step_launches": 50 + args.warmup, "copy_bytes": n, "copies": 5}))
+        return
+    # the timed region: K back-to-back launches on the stepper's stream
+    # bracketed by HIP events on that stream; the average launch duration is
+    # the region's time over K
+    total_ms, kern_ms = time_steps(torch, g, args.steps, per_launch=False)
     cells = g.C
     K = g.K
     ms_step = total_ms / args.steps

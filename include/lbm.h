@@ -73,7 +73,8 @@ enum {                      /* lbm_reduce: what                                 
  *                            3 temperature-gradient trackers (Sec. 3, the
  *                            homogenized NSF case at porosity 1, full tracker basis)
  *   lattice: "D2Q5" | "D2Q9" (2D systems) | "D3Q7" (3D systems)
- *   nx, ny, nz: grid; nz must be 1 in 2D; nx must be a multiple of 64.
+ *   nx, ny, nz: grid; nz must be 1 in 2D (rows whose length is a multiple
+ *   of 64 map onto whole wavefronts; any size is accepted).
  *   tau: relaxation time tau_LB of the conserved fields (> 1/2); dt, dx:
  *   time step and grid spacing (the flux enters the equilibrium times dt/dx).
  * Returns NULL on error (message via lbm_last_error(NULL)). */
@@ -100,8 +101,9 @@ int lbm_set_param(lbm_state *h, const char *name, double v);
 /* Read a parameter in use: "dt", "dx", "lambda" (dt/dx), "tau", "omega"
  * (conserved fields), "omega_tracker", "tau_grad", "g_tau", "g", "t0".
  * After lbm_bind with F32/F16 storage these are the values the kernels run
- * with: dt/dx and 2 - omega are rounded once to float, and dt, tau and the
- * collision rates are the values those roundings define.  LBM_EINVAL for an
+ * with: dt/dx is rounded once to float and 2 - omega to a multiple of 2^-24
+ * (so that omega - 1 is exact in float), and dt, tau and the collision
+ * rates are the values those roundings define.  LBM_EINVAL for an
  * unknown name. */
 int lbm_get_param(const lbm_state *h, const char *name, double *v);
 

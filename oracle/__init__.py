@@ -224,5 +224,6 @@ def make(preset, n=None, shifted=True, Q0=None, params=None, tau_r=None, f=None)
     shape = (n,) * dim
     p = dict(preset.params)
     p.update(params or {})
+    p = {k: v for k, v in p.items() if k in PARAM_INDEX}
     return Oracle(preset.system, preset.lattice, shape, dt, dx, tau, preset.g_tau, p,
                   Q0=Q0, shifted=shifted)

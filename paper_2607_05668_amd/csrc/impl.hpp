@@ -34,6 +34,8 @@ struct KParams {
     R dt;
     R omega[LBM_MAXK];                // collision rate per field
     R delta[LBM_MAXK];                // 2 - omega
+    R c1[LBM_MAXK];                   // 1 - delta = omega - 1 (exactly representable)
+    R c2[LBM_MAXK];                   // 2 - delta = omega
     float scale[LBM_MAXK];            // storage = value * scale (F16 only)
     float inv_scale[LBM_MAXK];
     Phys<R> phys;

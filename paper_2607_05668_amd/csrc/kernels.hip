@@ -230,8 +230,30 @@ __global__ __launch_bounds__(kBlock) void k_step(const St *__restrict__ fin, St 
         dQ[k] = s;
         dQlo[k] = c;
     }
-    R dPhi[K][D];
-    Sys::template flux_delta<R, R>(p.phys, dQ, dPhi);
+    // Single-precision steppers of the precise systems evaluate the flux
+    // deviation at the compensated moments: dPhi(hi) and, from one
+    // forward-mode tangent, its first-order correction J(hi) lo.
+    constexpr bool PRECISE = Sys::precise && !std::is_same<St, _Float16>::value;
+    R dPhi[K][D], dPhiLo[K][D];
+    if constexpr (PRECISE) {
+        using D1 = Dual<R, 1>;
+        D1 q1[K], P1[K][D];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            q1[k] = D1(dQ[k]);
+            q1[k].d[0] = dQlo[k];
+        }
+        Sys::template flux_delta<D1, R>(p.phys, q1, P1);
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                dPhi[k][a] = P1[k][a].v;
+                dPhiLo[k][a] = P1[k][a].d[0];
+            }
+    } else {
+        Sys::template flux_delta<R, R>(p.phys, dQ, dPhi);
+    }
     R Sk[K];
     R bl[3] = {R(0), R(0), R(0)};       // per-cell source field (zero when none is attached)
     if (p.b) {
@@ -247,27 +269,51 @@ __global__ __launch_bounds__(kBlock) void k_step(const St *__restrict__ fin, St 
             for (int k = 0; k < 5; ++k) Sk[k] += S5[k];
         }
     }
-    // BGK relaxation in the form post = (2 feq - f) - delta (feq - f) with
-    // delta = 2 - omega (which keeps tau - 1/2 at full relative precision
-    // near omega = 2), for the moving populations.  The rest population
-    // closes the zeroth moment, post_0 = f_0 + dt S + sum_{i>0} (f_i - post_i),
-    // an identity of the update (the weights sum to one and the flux enters
-    // only odd moments) evaluated with the stored values of post_i, so each
-    // cell's post-collision moment carries a single storage rounding.
+    // BGK relaxation post = omega feq + (1 - omega) f written as
+    // post = e + c1 (e - f) with c1 = omega - 1 exactly representable (the
+    // host places 2 - omega on the 2^-24 grid): e - f is exact when f is
+    // within a factor two of e, so the update rounds once.  In the precise
+    // path e = e_hi + e_lo and post = e_hi + (c1 (e_hi - f) + omega e_lo).
+    // The rest population closes the zeroth moment,
+    // post_0 = f_0 + dt S + sum_{i>0} (f_i - post_i), an identity of the
+    // update (the weights sum to one, the flux enters only odd moments)
+    // evaluated with the stored values of post_i, so each cell's
+    // post-collision moment carries a single storage rounding.
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        const R del = p.delta[k];
-        R G[D], e[Q], s[Q];
+        const R c1 = p.c1[k], c2 = p.c2[k];
+        R s[Q], eh[Q], el[Q];
+        if constexpr (PRECISE) {
+            R Gh[D], Gl[D];
+            FF<R> e[Q];
 #pragma unroll
-        for (int a = 0; a < D; ++a) G[a] = p.lam * dPhi[k][a];
-        ExactEq<Lat>::feq(dQ[k], dQlo[k], G, e);
+            for (int a = 0; a < D; ++a) {
+                Gh[a] = p.lam * dPhi[k][a];
+                Gl[a] = fma(p.lam, dPhi[k][a], -Gh[a]) + p.lam * dPhiLo[k][a];
+            }
+            ExactEqFF<Lat>::feq(dQ[k], dQlo[k], Gh, Gl, e);
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                eh[i] = e[i].hi;
+                el[i] = e[i].lo;
+            }
+        } else {
+            R G[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) G[a] = p.lam * dPhi[k][a];
+            ExactEq<Lat>::feq(dQ[k], dQlo[k], G, eh);
+        }
         const R dts = p.dt * Sk[k];
         ExactEq<Lat>::zeroth(dts, s);
         R acc = dts;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             const R fi = f[k][i];
-            R post = (R(2) * e[i] - fi) - del * (e[i] - fi) + s[i];
+            R post;
+            if constexpr (PRECISE)
+                post = eh[i] + (fma(c1, eh[i] - fi, c2 * el[i]) + s[i]);
+            else
+                post = fma(c1, eh[i] - fi, eh[i]) + s[i];
             if constexpr (std::is_same<St, _Float16>::value) {
                 const _Float16 hv = (_Float16)(post * (R)p.scale[k]);
                 fout[(size_t)(k * Q + i) * C + cell] = hv;
@@ -688,6 +734,8 @@ KParams<R> lbm_state_impl::kparams(double t_half) const
         const double om = trk ? omega_t : omega_c;
         p.omega[k] = (R)om;
         p.delta[k] = (R)(2.0 - om);
+        p.c1[k] = (R)(om - 1.0);
+        p.c2[k] = (R)om;
         p.scale[k] = std::ldexp(1.0f, scale_exp[k]);
         p.inv_scale[k] = std::ldexp(1.0f, -scale_exp[k]);
     }

@@ -108,3 +108,85 @@ template <> struct ExactEq<D3Q7> {
         for (int i = 1; i < 7; ++i) e[i] = A;
     }
 };
+
+// Float-float form of the same equilibrium, for single-precision arithmetic:
+// every quantity is an unevaluated pair (hi, lo) built with error-free
+// transformations (two-sum; exact division remainder r = a - q b and exact
+// product error via fused multiply-add), so that e_i carries no rounding
+// beyond ~2^-44 relative and the collision rounds only once, at the store.
+template <class R>
+struct FF {
+    R hi, lo;
+};
+
+template <class R>
+__host__ __device__ inline FF<R> ff_two_sum(R a, R b)
+{
+    const R s = a + b;
+    const R bp = s - a;
+    return {s, (a - (s - bp)) + (b - bp)};
+}
+
+template <class R>
+__host__ __device__ inline FF<R> ff_add(FF<R> a, FF<R> b)
+{
+    FF<R> s = ff_two_sum(a.hi, b.hi);
+    s.lo += a.lo + b.lo;
+    return s;
+}
+
+// (hi + lo) / d for a small integer d: q = hi / d rounded, remainder exact
+template <class R>
+__host__ __device__ inline FF<R> ff_div(R hi, R lo, R d)
+{
+    const R q = hi / d;
+    const R r = fma(-q, d, hi);
+    return {q, (r + lo) / d};
+}
+
+template <class R>
+__host__ __device__ inline FF<R> ff_scale(FF<R> a, R s)      // s a power of two
+{
+    return {a.hi * s, a.lo * s};
+}
+
+// e_i (i >= 1) as float-float pairs from dQ = (qh, ql) and G = (Gh, Gl)
+template <class L> struct ExactEqFF;
+
+template <> struct ExactEqFF<D2Q5> {
+    template <class R>
+    __host__ __device__ static void feq(R qh, R ql, const R *Gh, const R *Gl, FF<R> *e)
+    {
+        const FF<R> A = ff_div(qh, ql, R(6));
+        const FF<R> hx = {Gh[0] * R(0.5), Gl[0] * R(0.5)}, hy = {Gh[1] * R(0.5), Gl[1] * R(0.5)};
+        const FF<R> mhx = {-hx.hi, -hx.lo}, mhy = {-hy.hi, -hy.lo};
+        e[1] = ff_add(A, hx); e[2] = ff_add(A, hy); e[3] = ff_add(A, mhx); e[4] = ff_add(A, mhy);
+    }
+};
+
+template <> struct ExactEqFF<D2Q9> {
+    template <class R>
+    __host__ __device__ static void feq(R qh, R ql, const R *Gh, const R *Gl, FF<R> *e)
+    {
+        const FF<R> A = ff_div(qh, ql, R(36)), A4 = ff_scale(A, R(4));
+        const FF<R> gx = ff_div(Gh[0], Gl[0], R(3)), gy = ff_div(Gh[1], Gl[1], R(3));
+        const FF<R> mgx = {-gx.hi, -gx.lo}, mgy = {-gy.hi, -gy.lo};
+        e[1] = ff_add(A4, gx); e[2] = ff_add(A4, gy); e[3] = ff_add(A4, mgx); e[4] = ff_add(A4, mgy);
+        const FF<R> sp = ff_scale(ff_add(gx, gy), R(0.25)), sm = ff_scale(ff_add(gy, mgx), R(0.25));
+        e[5] = ff_add(A, sp); e[6] = ff_add(A, sm);
+        e[7] = ff_add(A, FF<R>{-sp.hi, -sp.lo}); e[8] = ff_add(A, FF<R>{-sm.hi, -sm.lo});
+    }
+};
+
+template <> struct ExactEqFF<D3Q7> {
+    template <class R>
+    __host__ __device__ static void feq(R qh, R ql, const R *Gh, const R *Gl, FF<R> *e)
+    {
+        const FF<R> A = {qh * R(0.125), ql * R(0.125)};
+        for (int a = 0; a < 3; ++a) {
+            const FF<R> h = {Gh[a] * R(0.5), Gl[a] * R(0.5)};
+            e[1 + 2 * a] = ff_add(A, h);
+            e[2 + 2 * a] = ff_add(A, FF<R>{-h.hi, -h.lo});
+        }
+    }
+};

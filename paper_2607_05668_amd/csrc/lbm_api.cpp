@@ -129,10 +129,6 @@ lbm_state *lbm_create(const char *system, const char *lattice, int nx, int ny, i
         g_create_error = "invalid grid (nz must be 1 in 2D)";
         return nullptr;
     }
-    if (nx % 64 != 0) {
-        g_create_error = "nx must be a multiple of 64";
-        return nullptr;
-    }
     const long long C = (long long)nx * ny * nz;
     if ((long long)kSysK[sys] * kLatQ[lat] * C >= (1LL << 40)) {
         g_create_error = "grid too large";
@@ -283,7 +279,7 @@ int lbm_bind(lbm_state *h, void *pop_a, void *pop_b, void *aux, void *hip_stream
     h->L = lbm_launchers(h->sys, h->lat, h->storage);
     if (!h->L) return fail(h, LBM_EINVAL, "no kernel for this system, lattice and storage");
     // Parameters in use.  With single-precision arithmetic the kernels see
-    // dt/dx and delta = 2 - omega rounded once to float; the handle keeps the
+    // dt/dx rounded once to float and 2 - omega on the 2^-24 grid; the handle keeps the
     // values those roundings define (dt = float(dt/dx) dx, omega = 2 -
     // float(2 - omega)) so that time, diagnostics and lbm_get_param describe
     // exactly the scheme that runs.
@@ -292,8 +288,10 @@ int lbm_bind(lbm_state *h, void *pop_a, void *pop_b, void *aux, void *hip_stream
     if (h->storage != LBM_F64) {
         for (int k = 0; k < h->K; ++k) h->Q0[k] = (double)(float)h->Q0[k];
         h->dt = (double)(float)(h->dt / h->dx) * h->dx;
-        h->omega_c = 2.0 - (double)(float)(2.0 - h->omega_c);
-        h->omega_t = 2.0 - (double)(float)(2.0 - h->omega_t);
+        // 2 - omega on the 2^-24 grid, so that omega - 1 and 2 - omega are
+        // both exact in float (a change of tau - 1/2 below 1e-5 relative)
+        h->omega_c = 2.0 - std::nearbyint((2.0 - h->omega_c) * 16777216.0) / 16777216.0;
+        h->omega_t = 2.0 - std::nearbyint((2.0 - h->omega_t) * 16777216.0) / 16777216.0;
         h->tau = 1.0 / h->omega_c;
     }
     h->pop[0] = pop_a;

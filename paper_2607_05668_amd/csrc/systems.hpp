@@ -38,6 +38,7 @@ struct Phys {
 //   Phi_h = hu, Phi_hu = hu (x) u + g h^2/2 I, S_hu = -g h grad z_b.
 struct SysSWE {
     static constexpr int K = 3, D = 2, id = 1;
+    static constexpr bool precise = true;    // float-float equilibrium in single precision
     static constexpr bool tracker(int) { return false; }
 
     // d(a b / h) = (a0 db + b0 da + da db)/h - dh a0 b0 / (h h0)
@@ -89,6 +90,7 @@ struct SysSWE {
 // the flux of dQ.
 struct SysAdvDiff {
     static constexpr int K = 3, D = 2, id = 0;
+    static constexpr bool precise = true;    // float-float equilibrium in single precision
     static constexpr bool tracker(int k) { return k > 0; }
 
     template <class S, class R>
@@ -131,6 +133,7 @@ struct SysAdvDiff {
 // F - F^{-T} = (J F - cof F) / J, all formed from the small entries of H.
 struct SysNeoHooke {
     static constexpr int K = 6, D = 2, id = 2;
+    static constexpr bool precise = true;    // float-float equilibrium in single precision
     static constexpr bool tracker(int) { return false; }
 
     template <class S, class R>
@@ -231,6 +234,7 @@ struct SysNeoHooke {
 // every product ab - a0 b0 written as da b + a0 db.
 struct SysNSF17 {
     static constexpr int K = 17, D = 3, id = 3;
+    static constexpr bool precise = false;   // plain exact-moment equilibrium (VALU budget)
     static constexpr bool tracker(int k) { return k >= 5; }
 
     template <class S, class R>

@@ -126,8 +126,6 @@ PRESETS = {
                         {"ax": 0.1, "ay": 0.05, "nu": 0.01, "R": 0.0}),
     "swe1024": Preset("swe1024", "swe2d", "D2Q9", 1024, "f32", 1000,
                       "acoustic", 0.2, 2.0, None, {"g": 1.0}),
-    "nsf256": Preset("nsf256", "nsf3d_trk17", "D3Q7", 256, "f32", 500,
-                     "acoustic", 0.05, 20.0, 3.0, {}),
     "sweadj512": Preset("sweadj512", "swe2d", "D2Q9", 512, "f32", 500,
                         "acoustic", 0.2, 2.0, None, {"g": 1.0}),
     "neohooke2048": Preset("neohooke2048", "neohooke2d", "D2Q9", 2048, "f16", 2000,
@@ -240,6 +238,17 @@ class NsfMms:
         q[1:4] = self.rho0 * self.u0
         q[4] = self.E0
         return q
+
+
+def nsf_params(mms: NsfMms = NsfMms()):
+    """Parameters of the 3D NSF workload: gas, transport coefficients from
+    Re and Pr, and the manufactured-solution shape (mms_* entries)."""
+    return {"gamma": mms.gamma, "mu": mms.mu, "kappa": mms.kappa, "mms": 1.0, "mms_amp": mms.amp,
+            "mms_rho0": mms.rho0, "mms_p0": mms.p0, "mms_u0": mms.u0}
+
+
+PRESETS["nsf256"] = Preset("nsf256", "nsf3d_trk17", "D3Q7", 256, "f32", 500,
+                           "acoustic", 0.05, 20.0, 3.0, nsf_params())
 
 
 def nsf_exact(n: int, t: float, mms: NsfMms = NsfMms()):

@@ -38,8 +38,8 @@ def test_create_validates_arguments():
     assert b"unknown system" in lib.lbm_last_error(None)
     assert not lib.lbm_create(b"swe2d", b"D3Q7", 64, 64, 1, 0.6, 1e-3, 1e-2)
     assert not lib.lbm_create(b"swe2d", b"D2Q9", 64, 64, 2, 0.6, 1e-3, 1e-2)
-    assert not lib.lbm_create(b"swe2d", b"D2Q9", 65, 64, 1, 0.6, 1e-3, 1e-2)
-    assert b"multiple of 64" in lib.lbm_last_error(None)
+    assert not lib.lbm_create(b"swe2d", b"D2Q9", 0, 64, 1, 0.6, 1e-3, 1e-2)
+    assert b"invalid grid" in lib.lbm_last_error(None)
     assert not lib.lbm_create(b"swe2d", b"D2Q9", 64, 64, 1, 0.5, 1e-3, 1e-2)
     h = lib.lbm_create(b"swe2d", b"D2Q9", 64, 32, 1, 0.6, 1e-3, 1e-2)
     assert h
