@@ -15,6 +15,8 @@ Cases:
   hv = 0.02 sin sin sin t + 0.03 over z_b = 0.01 sin(2 pi x) cos(2 pi y).
 * ``adr_paper``  -- the paper's advection-diffusion-reaction MMS
   (supplement, ADR MMS), with the tracker initialised at grad c.
+* ``neohooke_paper`` -- the paper's finite-strain elasticity MMS
+  (supplement, elasticity MMS) with mu_s/rho0 = 1, lambda_s/rho0 = 2.
 * ``nsf17``      -- the 3D compressible NSF manufactured solution with the
   shapes of the paper's homogenized-NSF MMS (porosity 1), conserved rows
   forced; tracker rows are forced only when ``force_trackers`` is set.
@@ -77,6 +79,31 @@ def adr_paper(u0=0.1, u1=-0.1, D=0.01, R=1.0, tau_grad=None):
     res_c = sp.diff(c, T) + _div(Phi_c, (X, Y)) - S_c
     fQ = sp.lambdify((X, Y, T), [c, gx, gy], "numpy")
     fS = sp.lambdify((X, Y, T), [res_c, sp.Integer(0), sp.Integer(0)], "numpy", cse=True)
+    return _wrap2(fQ), _wrap2(fS)
+
+
+# ------------------------------------------------------------ ELASTIC ----
+@functools.lru_cache(maxsize=None)
+def neohooke_paper(rho0=1.0, mu_s=1.0, lam_s=2.0, amp=0.06):
+    """The paper's neo-Hookean MMS (supplement, elasticity MMS): F = I + grad w,
+    v = d_t w for the printed displacement potential w of amplitude 0.06."""
+    A = sp.Float(amp)
+    w0 = A * (sp.sin(PI2 * X) * sp.sin(PI2 * Y) * sp.cos(T) + sp.sin(PI2 * X) * sp.cos(PI2 * Y) * sp.sin(T) / 2
+              + sp.cos(PI2 * (X + Y)) * sp.cos(T) / 4)
+    w1 = A * (sp.cos(PI2 * X) * sp.cos(PI2 * Y) * sp.sin(T) + sp.cos(PI2 * X) * sp.sin(PI2 * Y) * sp.cos(T) / 2
+              + sp.sin(PI2 * (X - Y)) * sp.sin(T) / 4)
+    w = [w0, w1]
+    F = [[sp.Integer(1 if a == b else 0) + sp.diff(w[a], (X, Y)[b]) for b in range(2)] for a in range(2)]
+    v = [sp.diff(w[a], T) for a in range(2)]
+    J = F[0][0] * F[1][1] - F[0][1] * F[1][0]
+    FiT = [[F[1][1] / J, -F[1][0] / J], [-F[0][1] / J, F[0][0] / J]]
+    P = [[mu_s * (F[a][c] - FiT[a][c]) + lam_s * sp.log(J) * FiT[a][c] for c in range(2)] for a in range(2)]
+    Q = [F[0][0], F[0][1], F[1][0], F[1][1], v[0], v[1]]
+    Phi = [[-v[a] if b == c else sp.Integer(0) for c in range(2)] for a in range(2) for b in range(2)]
+    Phi += [[-P[a][c] / rho0 for c in range(2)] for a in range(2)]
+    res = [sp.diff(Q[k], T) + _div(Phi[k], (X, Y)) for k in range(6)]
+    fQ = sp.lambdify((X, Y, T), Q, "numpy")
+    fS = sp.lambdify((X, Y, T), res, "numpy", cse=True)
     return _wrap2(fQ), _wrap2(fS)
 
 
