@@ -28,7 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E nameplate
 KERNEL_SOURCES = ["paper_2607_05668_amd/csrc/kernels.hip", "paper_2607_05668_amd/csrc/systems.hpp",
                   "paper_2607_05668_amd/csrc/lattices.hpp", "paper_2607_05668_amd/csrc/impl.hpp",
-                  "paper_2607_05668_amd/csrc/dual.hpp"]
+                  "paper_2607_05668_amd/csrc/dual.hpp", "paper_2607_05668_amd/csrc/device_common.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_swe1024.json")
 
 
@@ -161,6 +161,8 @@ def extra_runs(torch, lbm, inputs):
     one("swe2d_D2Q9_f32_2048", p, 2048, "f32", 200, 216, inputs.swe_initial(2048))
     p = inputs.PRESETS["neohooke2048"]
     one("neohooke2d_D2Q9_f16_2048", p, 2048, "f16", 200, 216, inputs.neohooke_initial(2048))
+    # binary16 non-equilibrium deviations + FP32 moments: 2 (K Q 2 + K 4) bytes
+    one("neohooke2d_D2Q9_f16ne_2048", p, 2048, "f16ne", 200, 264, inputs.neohooke_initial(2048))
     p = inputs.PRESETS["advdiff64"]
     one("advdiff_D2Q5_f64_64", p, 64, "f64", 200, 240, inputs.advdiff_initial(64))
     p = inputs.PRESETS["nsf256"]

@@ -29,9 +29,12 @@
  *    data.  A handle is not thread-safe.  Status codes are below; the text of
  *    the last error is available from lbm_last_error.
  *  - Storage precision: LBM_F64 stores and computes in double; LBM_F32
- *    stores and computes in float; LBM_F16 stores IEEE binary16 scaled by a
- *    per-field power of two and computes in float.  Reductions accumulate in
- *    double in every case.
+ *    stores and computes in float; LBM_F16 stores the shifted populations in
+ *    IEEE binary16 scaled by a per-field power of two and computes in float;
+ *    LBM_F16NE keeps each cell's moment deviations in float and stores in
+ *    binary16 only each population's deviation from that cell's own
+ *    equilibrium (2D systems; the receiving cell rebuilds the population from
+ *    the sender's moments).  Reductions accumulate in double in every case.
  */
 #ifndef LBM_H
 #define LBM_H
@@ -53,7 +56,7 @@ enum {
     LBM_ENONFINITE = -5     /* non-finite populations detected                   */
 };
 
-enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2 };
+enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2, LBM_F16NE = 3 };
 
 enum {                      /* lbm_reduce: what                                  */
     LBM_RED_SUMS = 0,       /* sum_x Q_k(x)                        -> K doubles  */
@@ -107,8 +110,9 @@ int lbm_set_param(lbm_state *h, const char *name, double v);
  * unknown name. */
 int lbm_get_param(const lbm_state *h, const char *name, double *v);
 
-/* Population storage LBM_F64 / LBM_F32 / LBM_F16, before lbm_bind.
- * Default: LBM_F32. */
+/* Population storage LBM_F64 / LBM_F32 / LBM_F16 / LBM_F16NE, before
+ * lbm_bind.  Default: LBM_F32.  LBM_F16NE has no adjoint and no moment
+ * history. */
 int lbm_set_storage(lbm_state *h, int storage);
 
 /* Reference state Q0 (K host doubles) of the shifted form, before lbm_bind.
@@ -120,7 +124,9 @@ int lbm_set_reference(lbm_state *h, const double *Q0);
 int lbm_get_reference(const lbm_state *h, double *Q0_out);
 
 /* Bytes the caller must provide: which = 0 one population buffer
- * (K*Q*cells*sizeof(storage)); which = 1 scratch for reductions. */
+ * (K*Q*cells*sizeof(storage); for LBM_F16NE the binary16 deviations padded
+ * to 256 bytes followed by K*cells floats of moments); which = 1 scratch for
+ * reductions. */
 size_t lbm_required_bytes(const lbm_state *h, int which);
 
 /* Bind caller-owned device memory: two population buffers (A/B, each

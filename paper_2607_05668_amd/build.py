@@ -29,14 +29,17 @@ def _run(cmd, verbose):
     subprocess.run(cmd, check=True)
 
 
-def build(verbose: bool = False, jobs: int = 2) -> str:
-    os.makedirs(OUT_DIR, exist_ok=True)
+def build(verbose: bool = False, jobs: int = 2, out_dir: str = OUT_DIR, defines=()) -> str:
+    """Compile the library into out_dir; defines: extra -D tuning macros."""
+    os.makedirs(out_dir, exist_ok=True)
+    lib = os.path.join(out_dir, "liblbm.so")
     objs = []
     procs = []
-    units = [("kernels.hip", True), ("lbm_api.cpp", True)]
+    units = [("kernels.hip", True), ("kernels_ne.hip", True), ("lbm_api.cpp", True)]
     for name, dev in units:
-        obj = os.path.join(OUT_DIR, os.path.splitext(name)[0] + ".o")
-        cmd = [HIPCC] + COMMON + (DEVICE if dev else []) + ["-c", os.path.join(SRC, name), "-o", obj]
+        obj = os.path.join(out_dir, os.path.splitext(name)[0] + ".o")
+        cmd = [HIPCC] + COMMON + ["-D" + d for d in defines] + (DEVICE if dev else []) + \
+            ["-c", os.path.join(SRC, name), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append(subprocess.Popen(cmd))
@@ -44,10 +47,10 @@ def build(verbose: bool = False, jobs: int = 2) -> str:
     rc = [p.wait() for p in procs]
     if any(rc):
         raise RuntimeError("hipcc failed")
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs, verbose)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

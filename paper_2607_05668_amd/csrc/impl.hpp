@@ -11,7 +11,16 @@
 enum { SYS_ADVDIFF = 0, SYS_SWE = 1, SYS_NEOHOOKE = 2, SYS_NSF17 = 3 };
 enum { LAT_D2Q5 = 0, LAT_D2Q9 = 1, LAT_D3Q7 = 2 };
 
-constexpr int kBlock = 256;          // threads per workgroup (4 waves of 64)
+#ifndef LBM_BLOCK
+#define LBM_BLOCK 256
+#endif
+#ifndef LBM_XCD_REMAP
+#define LBM_XCD_REMAP 1                 // consecutive tiles on one XCD
+#endif
+constexpr int kBlock = LBM_BLOCK;    // threads per workgroup (wave64 multiples)
+// Population buffers larger than this together (A + B) are written with
+// non-temporal stores: MI355X's Infinity Cache holds 256 MiB.
+constexpr size_t kLastLevelCacheBytes = (size_t)256 << 20;
 constexpr int kRedBlocks = 1024;     // workgroups of the first reduction pass
 
 // Manufactured-solution forcing of the 3D NSF system (conserved rows).
@@ -64,6 +73,7 @@ struct Launchers {
 };
 
 const Launchers *lbm_launchers(int sys, int lat, int storage);
+const Launchers *lbm_launchers_ne(int sys, int lat);   // storage LBM_F16NE
 hipError_t lbm_launch_copy(void *dst, const void *src, size_t n, hipStream_t s);
 
 // Host-side state behind the opaque lbm_state handle.

@@ -21,62 +21,7 @@
 #include <cstring>
 #include <type_traits>
 
-#include "impl.hpp"
-#include "lattices.hpp"
-
-// ----------------------------------------------------------- storage ----
-template <class St> struct Store;
-// ld/st convert between the stored type and the arithmetic type R; st_init
-// rounds a double once to the stored type (round to nearest even).
-template <> struct Store<double> {
-    using R = double;
-    __device__ static double ld(const double *p) { return *p; }
-    __device__ static void st(double *p, double v) { *p = v; }
-    __device__ static void st_init(double *p, double v) { *p = v; }
-};
-template <> struct Store<float> {
-    using R = float;
-    __device__ static float ld(const float *p) { return *p; }
-    __device__ static void st(float *p, float v) { *p = v; }
-    __device__ static void st_init(float *p, double v) { *p = (float)v; }
-};
-template <> struct Store<_Float16> {
-    using R = float;
-    __device__ static float ld(const _Float16 *p) { return (float)*p; }
-    __device__ static void st(_Float16 *p, float v) { *p = (_Float16)v; }
-    __device__ static void st_init(_Float16 *p, double v) { *p = (_Float16)v; }
-};
-
-// ------------------------------------------------------------ helpers ----
-__device__ inline long long xcd_tile(unsigned bid, unsigned nb)
-{
-    const unsigned q = nb >> 3, r = nb & 7u;
-    const unsigned x = bid & 7u, loc = bid >> 3;
-    return (long long)x * q + (x < r ? x : r) + loc;
-}
-
-__device__ inline int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
-
-template <class Lat>
-__device__ inline void neighbours(int x, int y, int z, int nx, int ny, int nz, int sign, long long *idx)
-{
-#pragma unroll
-    for (int i = 0; i < Lat::Q; ++i) {
-        const int xs = wrapi(x + sign * Lat::cx[i], nx);
-        const int ys = wrapi(y + sign * Lat::cy[i], ny);
-        const int zs = Lat::D == 3 ? wrapi(z + sign * Lat::cz[i], nz) : 0;
-        idx[i] = ((long long)zs * ny + ys) * nx + xs;
-    }
-}
-
-template <class R>
-__device__ inline void cell_coords(long long cell, int nx, int ny, int &x, int &y, int &z)
-{
-    const long long row = cell / nx;
-    x = (int)(cell - row * nx);
-    z = (int)(row / ny);
-    y = (int)(row - (long long)z * ny);
-}
+#include "device_common.hpp"
 
 // --------------------------------------------- manufactured forcing ----
 // d_t Q + div Phi(Q) for the 3D NSF manufactured solution (exact fields of
@@ -188,27 +133,42 @@ __device__ inline void nsf_mms_source(const MmsParams<R> &m, const Phys<R> &p, R
 }
 
 // ---------------------------------------------------- collide & stream ----
-template <class Sys, class Lat, class St, bool REC>
-__global__ __launch_bounds__(kBlock) void k_step(const St *__restrict__ fin, St *__restrict__ fout,
-                                                 const KParams<typename Store<St>::R> p,
-                                                 typename Store<St>::R *__restrict__ qhist)
+// Workgroup size of the step kernel.  The 17-field cascade keeps ~250
+// values live per cell: a 512-thread workgroup (two waves per SIMD) caps a
+// wave at 256 of the SIMD's 512 registers per lane, so two waves share each
+// SIMD and one hides the other's loads (in FP32 it needs 230, no spills).
+template <class Sys>
+constexpr int step_block() { return Sys::K > 6 ? 512 : kBlock; }
+
+template <class Sys, class Lat, class St, bool REC, bool NT, bool O32>
+__global__ __launch_bounds__(step_block<Sys>()) void k_step(const St *__restrict__ fin, St *__restrict__ fout,
+                                                            const KParams<typename Store<St>::R> p,
+                                                            typename Store<St>::R *__restrict__ qhist)
 {
     using R = typename Store<St>::R;
+    using I = typename Index<O32>::T;
     constexpr int K = Sys::K, Q = Lat::Q, D = Lat::D;
-    const long long cell = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (cell >= p.C) return;
+    constexpr I S = sizeof(St);
+    const I cell = (I)xcd_tile(blockIdx.x, gridDim.x) * step_block<Sys>() + threadIdx.x;
+    if (cell >= (I)p.C) return;
     int x, y, z;
-    cell_coords<R>(cell, p.nx, p.ny, x, y, z);
-    long long src[Q];
+    cell_coords(cell, p.nx, p.ny, x, y, z);
+    // byte offsets inside one field's [Q][cells] block: pulled population i
+    // and this cell's slot of population i
+    const I C = (I)p.C;
+    I src[Q];
     neighbours<Lat>(x, y, z, p.nx, p.ny, p.nz, -1, src);
-    const size_t C = (size_t)p.C;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) src[i] = ((I)i * C + src[i]) * S;
+    const I own = cell * S;
+    const size_t field = (size_t)Q * p.C;      // elements per field block
 
     R f[K][Q];
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const R v = Store<St>::ld(fin + (size_t)(k * Q + i) * C + src[i]);
+            const R v = Store<St>::ld(byte_at(fin + k * field, src[i]));
             if constexpr (std::is_same<St, _Float16>::value)
                 f[k][i] = v * (R)p.inv_scale[k];
             else
@@ -223,8 +183,10 @@ __global__ __launch_bounds__(kBlock) void k_step(const St *__restrict__ fin, St 
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             const R t = s + f[k][i];
-            const R bp = t - s;
-            c += (s - (t - bp)) + (f[k][i] - bp);
+            if constexpr (Sys::compensated) {
+                const R bp = t - s;
+                c += (s - (t - bp)) + (f[k][i] - bp);
+            }
             s = t;
         }
         dQ[k] = s;
@@ -258,7 +220,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const St *__restrict__ fin, St 
     R bl[3] = {R(0), R(0), R(0)};       // per-cell source field (zero when none is attached)
     if (p.b) {
 #pragma unroll
-        for (int a = 0; a < D; ++a) bl[a] = p.b[(size_t)a * C + cell];
+        for (int a = 0; a < D; ++a) bl[a] = *byte_at(p.b + a * (size_t)p.C, cell * (I)sizeof(R));
     }
     Sys::template source<R, R>(p.phys, dQ, bl, Sk);
     if constexpr (Sys::id == SYS_NSF17) {
@@ -314,22 +276,23 @@ __global__ __launch_bounds__(kBlock) void k_step(const St *__restrict__ fin, St 
                 post = eh[i] + (fma(c1, eh[i] - fi, c2 * el[i]) + s[i]);
             else
                 post = fma(c1, eh[i] - fi, eh[i]) + s[i];
+            St *dst = byte_at(fout + k * field, (I)i * C * S + own);
             if constexpr (std::is_same<St, _Float16>::value) {
                 const _Float16 hv = (_Float16)(post * (R)p.scale[k]);
-                fout[(size_t)(k * Q + i) * C + cell] = hv;
+                st_pop<NT>(dst, hv);
                 post = (R)hv * (R)p.inv_scale[k];
             } else {
-                Store<St>::st(fout + (size_t)(k * Q + i) * C + cell, post);
+                Store<St>::template st<NT>(dst, post);
             }
             acc += fi - post;
         }
         R rest = f[k][0] + acc;
         if constexpr (std::is_same<St, _Float16>::value) rest *= (R)p.scale[k];
-        Store<St>::st(fout + (size_t)(k * Q) * C + cell, rest);
+        Store<St>::template st<NT>(byte_at(fout + k * field, own), rest);
     }
     if constexpr (REC) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) qhist[(size_t)k * C + cell] = dQ[k];
+        for (int k = 0; k < K; ++k) *byte_at(qhist + k * (size_t)p.C, cell * (I)sizeof(R)) = dQ[k];
     }
 }
 
@@ -344,7 +307,7 @@ __global__ __launch_bounds__(kBlock) void k_init(const double *__restrict__ Qin,
     const long long cell = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (cell >= p.C) return;
     int x, y, z;
-    cell_coords<double>(cell, p.nx, p.ny, x, y, z);
+    cell_coords(cell, p.nx, p.ny, x, y, z);
     long long dst[Q];
     neighbours<Lat>(x, y, z, p.nx, p.ny, p.nz, -1, dst);
     const size_t C = (size_t)p.C;
@@ -365,33 +328,6 @@ __global__ __launch_bounds__(kBlock) void k_init(const double *__restrict__ Qin,
 }
 
 // per-block maxima of |f*eq_{k,i}| per field (chooses the F16 scales)
-template <class R>
-__device__ inline R block_reduce_max(R v, R *sh)
-{
-    for (int o = 32; o > 0; o >>= 1) {
-        const R w = __shfl_xor(v, o, 64);
-        v = w > v ? w : v;
-    }
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-    __syncthreads();
-    R r = sh[0];
-    for (int j = 1; j < kBlock / 64; ++j) r = sh[j] > r ? sh[j] : r;
-    __syncthreads();
-    return r;
-}
-
-template <class R>
-__device__ inline R block_reduce_sum(R v, R *sh)
-{
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-    __syncthreads();
-    R r = sh[0];
-    for (int j = 1; j < kBlock / 64; ++j) r += sh[j];
-    __syncthreads();
-    return r;
-}
-
 template <class Sys, class Lat>
 __global__ __launch_bounds__(kBlock) void k_init_absmax(const double *__restrict__ Qin, double *__restrict__ part,
                                                         const KParams<double> p)
@@ -434,7 +370,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(const St *__restrict__ fin, 
     const long long cell = (long long)blockIdx.x * kBlock + threadIdx.x;
     if (cell >= p.C) return;
     int x, y, z;
-    cell_coords<double>(cell, p.nx, p.ny, x, y, z);
+    cell_coords(cell, p.nx, p.ny, x, y, z);
     long long src[Q];
     neighbours<Lat>(x, y, z, p.nx, p.ny, p.nz, -1, src);
     const size_t C = (size_t)p.C;
@@ -476,7 +412,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce1(const St *__restrict__ fin, 
     for (int k = 0; k < K; ++k) a0[k] = a1[k] = 0.0;
     for (long long cell = (long long)blockIdx.x * kBlock + threadIdx.x; cell < p.C; cell += (long long)nb * kBlock) {
         int x, y, z;
-        cell_coords<double>(cell, p.nx, p.ny, x, y, z);
+        cell_coords(cell, p.nx, p.ny, x, y, z);
         long long src[Q];
         neighbours<Lat>(x, y, z, p.nx, p.ny, p.nz, -1, src);
         double q[K];
@@ -552,7 +488,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(const R *__restrict__ lin, 
     const long long cell = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (cell >= p.C) return;
     int x, y, z;
-    cell_coords<R>(cell, p.nx, p.ny, x, y, z);
+    cell_coords(cell, p.nx, p.ny, x, y, z);
     long long src[Q];
     neighbours<Lat>(x, y, z, p.nx, p.ny, p.nz, +1, src);
     const size_t C = (size_t)p.C;
@@ -687,10 +623,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_init(const R *__restrict__ lam0,
 }
 
 // ------------------------------------------------------ bandwidth probe --
-__global__ __launch_bounds__(kBlock) void k_copy(const float4 *__restrict__ src, float4 *__restrict__ dst, size_t n4)
+// One 16-byte vector per thread, non-temporal both ways: the fastest plain
+// copy measured on this part (the probe of achievable HBM bandwidth).
+typedef float v4f __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(kBlock) void k_copy(const v4f *__restrict__ src, v4f *__restrict__ dst, size_t n4)
 {
     const size_t i = (size_t)xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (i < n4) dst[i] = src[i];
+    if (i < n4) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 __global__ void k_copy_tail(const unsigned char *__restrict__ src, unsigned char *__restrict__ dst, size_t n)
@@ -704,7 +643,7 @@ hipError_t lbm_launch_copy(void *dst, const void *src, size_t n, hipStream_t s)
     const size_t n4 = n / 16;
     if (n4) {
         const size_t nb = (n4 + kBlock - 1) / kBlock;
-        hipLaunchKernelGGL(k_copy, dim3((unsigned)nb), dim3(kBlock), 0, s, (const float4 *)src, (float4 *)dst, n4);
+        hipLaunchKernelGGL(k_copy, dim3((unsigned)nb), dim3(kBlock), 0, s, (const v4f *)src, (v4f *)dst, n4);
     }
     const size_t tail = n - n4 * 16;
     if (tail)
@@ -818,16 +757,39 @@ struct Impl {
     using R = typename Store<St>::R;
     static unsigned grid(long long C) { return (unsigned)((C + kBlock - 1) / kBlock); }
 
+    template <bool REC, bool NT, bool O32>
+    static void launch_step(const lbm_state_impl &h, const void *fin, void *fout, void *qhist, hipStream_t s,
+                            const KParams<R> &p)
+    {
+        constexpr int B = step_block<Sys>();
+        hipLaunchKernelGGL((k_step<Sys, Lat, St, REC, NT, O32>), dim3((unsigned)((h.C + B - 1) / B)), dim3(B), 0,
+                           s, (const St *)fin, (St *)fout, p, (R *)qhist);
+    }
+    template <bool REC, bool NT>
+    static void launch_step(const lbm_state_impl &h, const void *fin, void *fout, void *qhist, hipStream_t s,
+                            const KParams<R> &p)
+    {
+        // the 32-bit form also needs the history and source planes in range
+        if (fits_o32(h.C, Lat::Q, sizeof(St)) && fits_o32(h.C, 1, sizeof(R)))
+            launch_step<REC, NT, true>(h, fin, fout, qhist, s, p);
+        else
+            launch_step<REC, NT, false>(h, fin, fout, qhist, s, p);
+    }
     static hipError_t step(const lbm_state_impl &h, const void *fin, void *fout, void *qhist, hipStream_t s)
     {
         const double t_half = h.t0 + (h.nsteps + 0.5) * h.dt;
         const KParams<R> p = h.kparams<R>(t_half);
-        if (qhist)
-            hipLaunchKernelGGL((k_step<Sys, Lat, St, true>), dim3(grid(h.C)), dim3(kBlock), 0, s, (const St *)fin,
-                               (St *)fout, p, (R *)qhist);
-        else
-            hipLaunchKernelGGL((k_step<Sys, Lat, St, false>), dim3(grid(h.C)), dim3(kBlock), 0, s, (const St *)fin,
-                               (St *)fout, p, (R *)nullptr);
+        const bool nt = 2 * (size_t)Sys::K * Lat::Q * sizeof(St) * (size_t)h.C > kLastLevelCacheBytes;
+        if constexpr (Sys::K <= 6) {
+            if (qhist) {
+                nt ? launch_step<true, true>(h, fin, fout, qhist, s, p)
+                   : launch_step<true, false>(h, fin, fout, qhist, s, p);
+                return hipGetLastError();
+            }
+        } else {
+            if (qhist) return hipErrorInvalidValue;   // no adjoint for the 3D cascade
+        }
+        nt ? launch_step<false, true>(h, fin, fout, qhist, s, p) : launch_step<false, false>(h, fin, fout, qhist, s, p);
         return hipGetLastError();
     }
     static hipError_t init(const lbm_state_impl &h, const double *Q, void *fout, hipStream_t s)
@@ -915,6 +877,7 @@ static const Launchers *by_storage(int storage)
 
 const Launchers *lbm_launchers(int sys, int lat, int storage)
 {
+    if (storage == 3) return lbm_launchers_ne(sys, lat);
     switch (sys) {
     case SYS_SWE:
         if (lat == LAT_D2Q5) return by_storage<SysSWE, D2Q5>(storage);
@@ -934,3 +897,6 @@ const Launchers *lbm_launchers(int sys, int lat, int storage)
     }
     return nullptr;
 }
+
+template KParams<float> lbm_state_impl::kparams<float>(double) const;
+template KParams<double> lbm_state_impl::kparams<double>(double) const;

@@ -1,0 +1,392 @@
+// FP16 storage of the deviation from the sender's local equilibrium
+// (storage LBM_F16NE).
+//
+// The paper stores the populations shifted by the background equilibrium
+// (Sec. 2.5.2).  In binary16 that leaves a rounding of ~2^-12 |f*| per
+// population per step, which over thousands of steps dominates fields that
+// start at zero.  This storage keeps, for every cell y, its pre-collision
+// moment deviations M(y) in FP32 and stores in binary16 only
+//     g_i(y) = post_i(y) - e_i(M(y)),
+// the deviation of each post-collision population from the cell's own
+// (shifted, exact-moment) equilibrium e_i(M) = w_i M + (w_i/cs^2) c_i.(dt/dx)
+// dPhi(M).  With post = e + (omega - 1)(e - f) + dt w_i S the stored value is
+// g_i = (omega - 1)(e_i - f_i) + dt w_i S (the non-equilibrium part), formed
+// without cancellation.  The receiver x = y + c_i rebuilds
+//     f_i(x) = g_i(x - c_i) + e_i(M(x - c_i))
+// by re-evaluating the flux at the sender's stored moments (the same float
+// computation as the sender's).  Per cell update this moves K Q 2 bytes of
+// populations and K 4 bytes of moments each way.
+//
+// Buffer layout (each of A and B): populations [K][Q][cells] binary16, padded
+// to 256 bytes, then moments [K][cells] float.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "device_common.hpp"
+
+inline size_t ne_pop_bytes(long long C, int K, int Q) { return (((size_t)K * Q * C * 2) + 255) & ~(size_t)255; }
+
+// Rebuild the pre-collision populations of cell (x, y, z) from the senders'
+// deviations and stored moments.
+template <class Sys, class Lat>
+__device__ inline void ne_load(const _Float16 *__restrict__ g, const float *__restrict__ M, const KParams<float> &p,
+                               const long long *src, float f[][Lat::Q])
+{
+    constexpr int K = Sys::K, Q = Lat::Q, D = Lat::D;
+    const size_t C = (size_t)p.C;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        float My[K], ei[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) My[k] = M[(size_t)k * C + src[i]];
+        if (i == 0) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) ei[k] = ExactEq<Lat>::rest(My[k]);
+        } else {
+            float P[K][D];
+            Sys::template flux_delta<float, float>(p.phys, My, P);
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                float G[D], e[Q];
+#pragma unroll
+                for (int a = 0; a < D; ++a) G[a] = p.lam * P[k][a];
+                ExactEq<Lat>::feq(My[k], 0.0f, G, e);
+                ei[k] = e[i];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            f[k][i] = (float)g[(size_t)(k * Q + i) * C + src[i]] * p.inv_scale[k] + ei[k];
+    }
+}
+
+template <class Sys, class Lat, bool NT>
+__global__ __launch_bounds__(kBlock) void k_step_ne(const _Float16 *__restrict__ gin, const float *__restrict__ Min,
+                                                    _Float16 *__restrict__ gout, float *__restrict__ Mout,
+                                                    const KParams<float> p)
+{
+    constexpr int K = Sys::K, Q = Lat::Q, D = Lat::D;
+    const long long cell = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (cell >= p.C) return;
+    int x, y, z;
+    cell_coords(cell, p.nx, p.ny, x, y, z);
+    long long src[Q];
+    neighbours<Lat>(x, y, z, p.nx, p.ny, p.nz, -1, src);
+    const size_t C = (size_t)p.C;
+    float f[K][Q];
+    ne_load<Sys, Lat>(gin, Min, p, src, f);
+    float dQ[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        float s = f[k][0];
+#pragma unroll
+        for (int i = 1; i < Q; ++i) s += f[k][i];
+        dQ[k] = s;
+    }
+    float dPhi[K][D];
+    Sys::template flux_delta<float, float>(p.phys, dQ, dPhi);
+    float Sk[K];
+    float bl[3] = {0.0f, 0.0f, 0.0f};
+    if (p.b) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) bl[a] = p.b[(size_t)a * C + cell];
+    }
+    Sys::template source<float, float>(p.phys, dQ, bl, Sk);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        float G[D], e[Q], s[Q];
+#pragma unroll
+        for (int a = 0; a < D; ++a) G[a] = p.lam * dPhi[k][a];
+        ExactEq<Lat>::feq(dQ[k], 0.0f, G, e);
+        const float e0 = ExactEq<Lat>::rest(dQ[k]);
+        const float dts = p.dt * Sk[k];
+        ExactEq<Lat>::zeroth(dts, s);
+        float acc = dts;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const float d = e[i] - f[k][i];
+            const _Float16 hv = (_Float16)(fmaf(p.c1[k], d, s[i]) * p.scale[k]);
+            st_pop<NT>(gout + (size_t)(k * Q + i) * C + cell, hv);
+            acc += (f[k][i] - e[i]) - (float)hv * p.inv_scale[k];
+        }
+        const float g0 = (f[k][0] - e0) + acc;
+        st_pop<NT>(gout + (size_t)(k * Q) * C + cell, (_Float16)(g0 * p.scale[k]));
+        st_pop<NT>(Mout + (size_t)k * C + cell, dQ[k]);
+    }
+}
+
+// Initial state: M(y) = Q(y) - Q0 rounded to float and, in the pull layout,
+// g_i(y) = f*eq_i(Q(y + c_i)) - e_i(M(y)) with the equilibrium of the
+// receiver's initial fields in double and e_i(M) as the step kernel forms it.
+template <class Sys, class Lat, bool STORE>
+__device__ inline void ne_init_cell(const double *__restrict__ Qin, const KParams<double> &pd,
+                                    const KParams<float> &pf, long long cell, _Float16 *g, float *M, double *mx)
+{
+    constexpr int K = Sys::K, Q = Lat::Q, D = Lat::D;
+    const size_t C = (size_t)pd.C;
+    int x, y, z;
+    cell_coords(cell, pd.nx, pd.ny, x, y, z);
+    long long dst[Q];
+    neighbours<Lat>(x, y, z, pd.nx, pd.ny, pd.nz, +1, dst);
+    float My[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) My[k] = (float)(Qin[(size_t)k * C + cell] - pd.phys.Q0[k]);
+    float Pm[K][D];
+    Sys::template flux_delta<float, float>(pf.phys, My, Pm);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        // receiver's initial equilibrium in double
+        double dq[K], P[K][D];
+#pragma unroll
+        for (int k = 0; k < K; ++k) dq[k] = Qin[(size_t)k * C + dst[i]] - pd.phys.Q0[k];
+        Sys::template flux_delta<double, double>(pd.phys, dq, P);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double cd = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) cd += lat_c<Lat>(i, a) * P[k][a];
+            const double feq = Lat::w[i] * (dq[k] + pd.lam_cs2 * cd);
+            float ei;
+            if (i == 0) {
+                ei = ExactEq<Lat>::rest(My[k]);
+            } else {
+                float G[D], e[Q];
+#pragma unroll
+                for (int a = 0; a < D; ++a) G[a] = pf.lam * Pm[k][a];
+                ExactEq<Lat>::feq(My[k], 0.0f, G, e);
+                ei = e[i];
+            }
+            const double gv = feq - (double)ei;
+            if constexpr (STORE)
+                g[(size_t)(k * Q + i) * C + cell] = (_Float16)(gv * (double)pf.scale[k]);
+            else
+                mx[k] = fabs(gv) > mx[k] ? fabs(gv) : mx[k];
+        }
+    }
+    if constexpr (STORE) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) M[(size_t)k * C + cell] = My[k];
+    }
+}
+
+template <class Sys, class Lat>
+__global__ __launch_bounds__(kBlock) void k_init_ne(const double *__restrict__ Qin, _Float16 *__restrict__ g,
+                                                    float *__restrict__ M, const KParams<double> pd,
+                                                    const KParams<float> pf)
+{
+    const long long cell = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (cell >= pd.C) return;
+    ne_init_cell<Sys, Lat, true>(Qin, pd, pf, cell, g, M, nullptr);
+}
+
+template <class Sys, class Lat>
+__global__ __launch_bounds__(kBlock) void k_init_absmax_ne(const double *__restrict__ Qin, double *__restrict__ part,
+                                                           const KParams<double> pd, const KParams<float> pf)
+{
+    constexpr int K = Sys::K;
+    __shared__ double sh[kBlock / 64];
+    double mx[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) mx[k] = 0.0;
+    for (long long cell = (long long)blockIdx.x * kBlock + threadIdx.x; cell < pd.C;
+         cell += (long long)gridDim.x * kBlock)
+        ne_init_cell<Sys, Lat, false>(Qin, pd, pf, cell, nullptr, nullptr, mx);
+    for (int k = 0; k < K; ++k) {
+        const double r = block_reduce_max(mx[k], sh);
+        if (threadIdx.x == 0) part[(size_t)k * gridDim.x + blockIdx.x] = r;
+    }
+}
+
+template <class Sys, class Lat, class Out>
+__global__ __launch_bounds__(kBlock) void k_moments_ne(const _Float16 *__restrict__ g, const float *__restrict__ M,
+                                                       Out *__restrict__ out, const KParams<float> p,
+                                                       const KParams<double> pd, int absolute)
+{
+    constexpr int K = Sys::K, Q = Lat::Q;
+    const long long cell = (long long)blockIdx.x * kBlock + threadIdx.x;
+    if (cell >= p.C) return;
+    int x, y, z;
+    cell_coords(cell, p.nx, p.ny, x, y, z);
+    long long src[Q];
+    neighbours<Lat>(x, y, z, p.nx, p.ny, p.nz, -1, src);
+    float f[K][Q];
+    ne_load<Sys, Lat>(g, M, p, src, f);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) s += (double)f[k][i];
+        out[(size_t)k * (size_t)p.C + cell] = (Out)(absolute ? s + pd.phys.Q0[k] : s);
+    }
+}
+
+template <class Sys, class Lat>
+__global__ __launch_bounds__(kBlock) void k_reduce1_ne(const _Float16 *__restrict__ g, const float *__restrict__ M,
+                                                       const double *__restrict__ ref, double *__restrict__ part,
+                                                       const KParams<float> p, const KParams<double> pd, int what)
+{
+    constexpr int K = Sys::K, Q = Lat::Q;
+    __shared__ double sh[kBlock / 64];
+    const size_t C = (size_t)p.C;
+    const unsigned nb = gridDim.x;
+    if (what == 4) {
+        double cnt = 0.0;
+        const size_t n = (size_t)K * Q * C;
+        for (size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (size_t)nb * kBlock)
+            cnt += isfinite((float)g[j]) ? 0.0 : 1.0;
+        for (size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x; j < (size_t)K * C; j += (size_t)nb * kBlock)
+            cnt += isfinite(M[j]) ? 0.0 : 1.0;
+        const double r = block_reduce_sum(cnt, sh);
+        if (threadIdx.x == 0) part[blockIdx.x] = r;
+        return;
+    }
+    double a0[K], a1[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) a0[k] = a1[k] = 0.0;
+    for (long long cell = (long long)blockIdx.x * kBlock + threadIdx.x; cell < p.C; cell += (long long)nb * kBlock) {
+        int x, y, z;
+        cell_coords(cell, p.nx, p.ny, x, y, z);
+        long long src[Q];
+        neighbours<Lat>(x, y, z, p.nx, p.ny, p.nz, -1, src);
+        float f[K][Q];
+        ne_load<Sys, Lat>(g, M, p, src, f);
+        double q[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) s += (double)f[k][i];
+            q[k] = s + pd.phys.Q0[k];
+        }
+        if (what == 0) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) a0[k] += q[k];
+        } else if (what == 1) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const double r = ref[(size_t)k * C + cell];
+                a0[k] += (q[k] - r) * (q[k] - r);
+                a1[k] += r * r;
+            }
+        } else if (what == 2) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const double r = ref[(size_t)k * C + cell];
+                const double e = fabs(q[k] - r);
+                a0[k] = e > a0[k] ? e : a0[k];
+                a1[k] = fabs(r) > a1[k] ? fabs(r) : a1[k];
+            }
+        } else {
+            const double sp = Sys::template max_speed<double>(pd.phys, q);
+            a0[0] = sp > a0[0] ? sp : a0[0];
+        }
+    }
+    const int nslot = (what == 3) ? 1 : (what == 0 ? K : 2 * K);
+    for (int j = 0; j < nslot; ++j) {
+        const double v = j < K ? a0[j] : a1[j - K];
+        const double r = (what == 2 || what == 3) ? block_reduce_max(v, sh) : block_reduce_sum(v, sh);
+        if (threadIdx.x == 0) part[(size_t)j * nb + blockIdx.x] = r;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce2_ne(const double *__restrict__ part, double *__restrict__ out,
+                                                       int nslot, int nb, int is_max)
+{
+    __shared__ double sh[kBlock / 64];
+    for (int j = 0; j < nslot; ++j) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < nb; b += kBlock) {
+            const double w = part[(size_t)j * nb + b];
+            v = is_max ? (w > v ? w : v) : v + w;
+        }
+        const double r = is_max ? block_reduce_max(v, sh) : block_reduce_sum(v, sh);
+        if (threadIdx.x == 0) out[j] = r;
+    }
+}
+
+template <class Sys, class Lat>
+struct ImplNE {
+    static unsigned grid(long long C) { return (unsigned)((C + kBlock - 1) / kBlock); }
+    static const _Float16 *gp(const lbm_state_impl &, const void *buf) { return (const _Float16 *)buf; }
+    static const float *mp(const lbm_state_impl &h, const void *buf)
+    {
+        return (const float *)((const char *)buf + ne_pop_bytes(h.C, Sys::K, Lat::Q));
+    }
+
+    static hipError_t step(const lbm_state_impl &h, const void *fin, void *fout, void *qhist, hipStream_t s)
+    {
+        if (qhist) return hipErrorInvalidValue;
+        const KParams<float> p = h.kparams<float>(h.t0 + (h.nsteps + 0.5) * h.dt);
+        const bool nt = 2 * (ne_pop_bytes(h.C, Sys::K, Lat::Q) + (size_t)Sys::K * h.C * 4) > kLastLevelCacheBytes;
+        if (nt)
+            hipLaunchKernelGGL((k_step_ne<Sys, Lat, true>), dim3(grid(h.C)), dim3(kBlock), 0, s, gp(h, fin),
+                               mp(h, fin), (_Float16 *)fout, (float *)mp(h, fout), p);
+        else
+            hipLaunchKernelGGL((k_step_ne<Sys, Lat, false>), dim3(grid(h.C)), dim3(kBlock), 0, s, gp(h, fin),
+                               mp(h, fin), (_Float16 *)fout, (float *)mp(h, fout), p);
+        return hipGetLastError();
+    }
+    static hipError_t init(const lbm_state_impl &h, const double *Q, void *fout, hipStream_t s)
+    {
+        hipLaunchKernelGGL((k_init_ne<Sys, Lat>), dim3(grid(h.C)), dim3(kBlock), 0, s, Q, (_Float16 *)fout,
+                           (float *)mp(h, fout), h.kparams<double>(h.t0), h.kparams<float>(h.t0));
+        return hipGetLastError();
+    }
+    static hipError_t init_absmax(const lbm_state_impl &h, const double *Q, double *part, hipStream_t s)
+    {
+        hipLaunchKernelGGL((k_init_absmax_ne<Sys, Lat>), dim3(kRedBlocks), dim3(kBlock), 0, s, Q, part,
+                           h.kparams<double>(h.t0), h.kparams<float>(h.t0));
+        return hipGetLastError();
+    }
+    static hipError_t moments(const lbm_state_impl &h, const void *fin, void *out, int absolute, int out_dtype,
+                              hipStream_t s)
+    {
+        const KParams<float> p = h.kparams<float>(h.t0);
+        const KParams<double> pd = h.kparams<double>(h.t0);
+        if (out_dtype == 0)
+            hipLaunchKernelGGL((k_moments_ne<Sys, Lat, double>), dim3(grid(h.C)), dim3(kBlock), 0, s, gp(h, fin),
+                               mp(h, fin), (double *)out, p, pd, absolute);
+        else
+            hipLaunchKernelGGL((k_moments_ne<Sys, Lat, float>), dim3(grid(h.C)), dim3(kBlock), 0, s, gp(h, fin),
+                               mp(h, fin), (float *)out, p, pd, absolute);
+        return hipGetLastError();
+    }
+    static hipError_t reduce(const lbm_state_impl &h, const void *fin, int what, const double *ref, double *aux,
+                             hipStream_t s)
+    {
+        hipLaunchKernelGGL((k_reduce1_ne<Sys, Lat>), dim3(kRedBlocks), dim3(kBlock), 0, s, gp(h, fin), mp(h, fin), ref,
+                           aux, h.kparams<float>(h.t0), h.kparams<double>(h.t0), what);
+        const int nslot = (what == 3 || what == 4) ? 1 : (what == 0 ? Sys::K : 2 * Sys::K);
+        const int is_max = (what == 2 || what == 3) ? 1 : 0;
+        hipLaunchKernelGGL(k_reduce2_ne, dim3(1), dim3(kBlock), 0, s, aux, aux + (size_t)2 * LBM_MAXK * kRedBlocks,
+                           nslot, kRedBlocks, is_max);
+        return hipGetLastError();
+    }
+    static const Launchers *get()
+    {
+        static const Launchers L = {Sys::K, Lat::Q, Lat::D, 2, step, init, init_absmax, moments,
+                                    reduce, nullptr, nullptr, nullptr};
+        return &L;
+    }
+};
+
+const Launchers *lbm_launchers_ne(int sys, int lat)
+{
+    switch (sys) {
+    case SYS_SWE:
+        if (lat == LAT_D2Q5) return ImplNE<SysSWE, D2Q5>::get();
+        if (lat == LAT_D2Q9) return ImplNE<SysSWE, D2Q9>::get();
+        break;
+    case SYS_ADVDIFF:
+        if (lat == LAT_D2Q5) return ImplNE<SysAdvDiff, D2Q5>::get();
+        if (lat == LAT_D2Q9) return ImplNE<SysAdvDiff, D2Q9>::get();
+        break;
+    case SYS_NEOHOOKE:
+        if (lat == LAT_D2Q5) return ImplNE<SysNeoHooke, D2Q5>::get();
+        if (lat == LAT_D2Q9) return ImplNE<SysNeoHooke, D2Q9>::get();
+        break;
+    }
+    return nullptr;
+}

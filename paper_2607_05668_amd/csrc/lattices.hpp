@@ -7,6 +7,28 @@
 // order is part of the ABI (see include/lbm.h).
 #pragma once
 
+#include <type_traits>
+
+// x / D, correctly rounded, for the weight denominators D = 3 and 9 in
+// single precision without a division instruction: q0 = x RN(1/D) is within
+// an ulp of x / D, the remainder x - q0 D is exact (fma), and one correction
+// q0 + r RN(1/D) rounds to the quotient.  For these two divisors the result
+// equals the IEEE quotient for every finite float (checked exhaustively over
+// all 2^31 magnitudes, subnormals included); 6 and 36 are reached through
+// power-of-two scalings, exact wherever the quotient is a normal number.
+// Other precisions divide.
+template <int D, class R>
+__host__ __device__ inline R div_by(R x)
+{
+    if constexpr (std::is_same<R, float>::value && (D == 3 || D == 9)) {
+        constexpr float r = 1.0f / D;
+        const float q0 = x * r;
+        return fmaf(fmaf(-q0, (float)D, x), r, q0);
+    } else {
+        return x / R(D);
+    }
+}
+
 struct D2Q5 {
     static constexpr int D = 2, Q = 5;
     static constexpr int cx[Q] = {0, 1, 0, -1, 0};
@@ -55,48 +77,52 @@ __host__ __device__ constexpr int lat_c(int i, int a)
 // Exact-moment equilibrium.  With e_i = w_i dQ + (w_i / cs^2) c_i . G,
 // G = (dt/dx) dPhi, the weights are written as exact rationals so that in
 // floating point the lattice moments of e carry only value-dependent
-// (unbiased) rounding: w_i dQ is one correctly rounded division followed by
-// power-of-two scalings, and the flux part is G / 3 (D2Q9) or G / 2 (D2Q5,
+// (unbiased) rounding: w_i dQ is one correctly rounded division (div_by)
+// followed by power-of-two scalings, and the flux part is G / 3 (D2Q9) or G / 2 (D2Q5,
 // D3Q7) with power-of-two scalings.  Rounding the weights themselves would
 // bias every cell's moments by the same relative amount, which the nearly
 // undamped non-equilibrium moments at omega -> 2 accumulate.  e_0 (rest) is
 // not formed: the collision closes the zeroth moment through the rest
-// population.  The zeroth part takes the moment as an unevaluated sum
+// population (`rest` gives w_0 M in the same exact form where a rest value is
+// needed).  The zeroth part takes the moment as an unevaluated sum
 // dQ = hi + lo (compensated summation), w_i dQ = w_i hi + w_i lo.
 // `zeroth` gives w_i s for i >= 1 (used for the source term).
 template <class L> struct ExactEq;
 
 template <> struct ExactEq<D2Q5> {
+    template <class R> __host__ __device__ static R rest(R M) { return div_by<3>(M); }
     template <class R> __host__ __device__ static void feq(R hi, R lo, const R *G, R *e)
     {
-        const R A = hi / R(6) + lo / R(6), hx = G[0] * R(0.5), hy = G[1] * R(0.5);
+        const R A = div_by<3>(hi) * R(0.5) + div_by<3>(lo) * R(0.5), hx = G[0] * R(0.5), hy = G[1] * R(0.5);
         e[1] = A + hx; e[2] = A + hy; e[3] = A - hx; e[4] = A - hy;
     }
     template <class R> __host__ __device__ static void zeroth(R s, R *e)
     {
-        const R A = s / R(6);
+        const R A = div_by<3>(s) * R(0.5);
         e[1] = A; e[2] = A; e[3] = A; e[4] = A;
     }
 };
 
 template <> struct ExactEq<D2Q9> {
+    template <class R> __host__ __device__ static R rest(R M) { return div_by<9>(M) * R(4); }
     template <class R> __host__ __device__ static void feq(R hi, R lo, const R *G, R *e)
     {
-        const R A = hi / R(36) + lo / R(36), A4 = A * R(4);
-        const R gx = G[0] / R(3), gy = G[1] / R(3);
+        const R A = div_by<9>(hi) * R(0.25) + div_by<9>(lo) * R(0.25), A4 = A * R(4);
+        const R gx = div_by<3>(G[0]), gy = div_by<3>(G[1]);
         e[1] = A4 + gx; e[2] = A4 + gy; e[3] = A4 - gx; e[4] = A4 - gy;
         e[5] = A + (gx + gy) * R(0.25); e[6] = A + (gy - gx) * R(0.25);
         e[7] = A - (gx + gy) * R(0.25); e[8] = A + (gx - gy) * R(0.25);
     }
     template <class R> __host__ __device__ static void zeroth(R s, R *e)
     {
-        const R A = s / R(36), A4 = A * R(4);
+        const R A = div_by<9>(s) * R(0.25), A4 = A * R(4);
         e[1] = A4; e[2] = A4; e[3] = A4; e[4] = A4;
         e[5] = A; e[6] = A; e[7] = A; e[8] = A;
     }
 };
 
 template <> struct ExactEq<D3Q7> {
+    template <class R> __host__ __device__ static R rest(R M) { return M * R(0.25); }
     template <class R> __host__ __device__ static void feq(R hi, R lo, const R *G, R *e)
     {
         const R A = hi * R(0.125) + lo * R(0.125), hx = G[0] * R(0.5), hy = G[1] * R(0.5), hz = G[2] * R(0.5);
@@ -135,13 +161,15 @@ __host__ __device__ inline FF<R> ff_add(FF<R> a, FF<R> b)
     return s;
 }
 
-// (hi + lo) / d for a small integer d: q = hi / d rounded, remainder exact
-template <class R>
-__host__ __device__ inline FF<R> ff_div(R hi, R lo, R d)
+// (hi + lo) / (B P) for B = 3 or 9 and a power of two P: q = RN(hi / (B P)),
+// the remainder hi - q B P is exact, and the low part (r + lo) / (B P) needs
+// no correct rounding.
+template <int B, class R>
+__host__ __device__ inline FF<R> ff_div(R hi, R lo, R P)
 {
-    const R q = hi / d;
-    const R r = fma(-q, d, hi);
-    return {q, (r + lo) / d};
+    const R q = div_by<B>(hi) / P;
+    const R r = fma(-q, R(B) * P, hi);
+    return {q, div_by<B>(r + lo) / P};
 }
 
 template <class R>
@@ -157,7 +185,7 @@ template <> struct ExactEqFF<D2Q5> {
     template <class R>
     __host__ __device__ static void feq(R qh, R ql, const R *Gh, const R *Gl, FF<R> *e)
     {
-        const FF<R> A = ff_div(qh, ql, R(6));
+        const FF<R> A = ff_div<3>(qh, ql, R(2));
         const FF<R> hx = {Gh[0] * R(0.5), Gl[0] * R(0.5)}, hy = {Gh[1] * R(0.5), Gl[1] * R(0.5)};
         const FF<R> mhx = {-hx.hi, -hx.lo}, mhy = {-hy.hi, -hy.lo};
         e[1] = ff_add(A, hx); e[2] = ff_add(A, hy); e[3] = ff_add(A, mhx); e[4] = ff_add(A, mhy);
@@ -168,8 +196,8 @@ template <> struct ExactEqFF<D2Q9> {
     template <class R>
     __host__ __device__ static void feq(R qh, R ql, const R *Gh, const R *Gl, FF<R> *e)
     {
-        const FF<R> A = ff_div(qh, ql, R(36)), A4 = ff_scale(A, R(4));
-        const FF<R> gx = ff_div(Gh[0], Gl[0], R(3)), gy = ff_div(Gh[1], Gl[1], R(3));
+        const FF<R> A = ff_div<9>(qh, ql, R(4)), A4 = ff_scale(A, R(4));
+        const FF<R> gx = ff_div<3>(Gh[0], Gl[0], R(1)), gy = ff_div<3>(Gh[1], Gl[1], R(1));
         const FF<R> mgx = {-gx.hi, -gx.lo}, mgy = {-gy.hi, -gy.lo};
         e[1] = ff_add(A4, gx); e[2] = ff_add(A4, gy); e[3] = ff_add(A4, mgx); e[4] = ff_add(A4, mgy);
         const FF<R> sp = ff_scale(ff_add(gx, gy), R(0.25)), sm = ff_scale(ff_add(gy, mgx), R(0.25));

@@ -233,7 +233,7 @@ int lbm_set_storage(lbm_state *h, int storage)
 {
     if (!h) return LBM_EINVAL;
     if (h->bound) return fail(h, LBM_EINVAL, "storage is fixed once bound");
-    if (storage < LBM_F64 || storage > LBM_F16) return fail(h, LBM_EINVAL, "unknown storage");
+    if (storage < LBM_F64 || storage > LBM_F16NE) return fail(h, LBM_EINVAL, "unknown storage");
     h->storage = storage;
     return LBM_OK;
 }
@@ -261,6 +261,8 @@ size_t lbm_required_bytes(const lbm_state *h, int which)
 {
     if (!h) return 0;
     if (which == 0) {
+        if (h->storage == LBM_F16NE)   // binary16 deviations, padded, then FP32 moments
+            return ((((size_t)h->K * h->Q * (size_t)h->C * 2) + 255) & ~(size_t)255) + (size_t)h->K * h->C * 4;
         const size_t s = h->storage == LBM_F64 ? 8 : (h->storage == LBM_F32 ? 4 : 2);
         return (size_t)h->K * h->Q * (size_t)h->C * s;
     }
@@ -322,8 +324,9 @@ int lbm_init_moments(lbm_state *h, const double *Q_dev)
     if (!Q_dev) return fail(h, LBM_EINVAL, "null field pointer");
     hipError_t e;
     for (int k = 0; k < LBM_MAXK; ++k) h->scale_exp[k] = 0;
-    if (h->storage == LBM_F16) {
-        // per-field power-of-two scale: the largest initial |f*| maps near 2^11
+    if (h->storage == LBM_F16 || h->storage == LBM_F16NE) {
+        // per-field power-of-two scale: the largest initial stored magnitude
+        // maps near 2^11 (binary16 holds up to 65504)
         e = h->L->init_absmax(*h, Q_dev, (double *)h->aux, h->stream);
         if (e != hipSuccess) return hipfail(h, e, "init_absmax");
         std::vector<double> part((size_t)h->K * kRedBlocks);
@@ -377,6 +380,7 @@ int lbm_step(lbm_state *h, int n) { return run_steps(h, n, nullptr); }
 int lbm_step_record(lbm_state *h, int n, void *Q_hist_dev)
 {
     if (h && !Q_hist_dev) return fail(h, LBM_EINVAL, "null history pointer");
+    if (h && h->storage == LBM_F16NE) return fail(h, LBM_EINVAL, "no moment history with F16NE storage");
     return run_steps(h, n, Q_hist_dev);
 }
 

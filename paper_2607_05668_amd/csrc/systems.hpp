@@ -39,6 +39,7 @@ struct Phys {
 struct SysSWE {
     static constexpr int K = 3, D = 2, id = 1;
     static constexpr bool precise = true;    // float-float equilibrium in single precision
+    static constexpr bool compensated = true;   // two-sum moments dQ = hi + lo
     static constexpr bool tracker(int) { return false; }
 
     // d(a b / h) = (a0 db + b0 da + da db)/h - dh a0 b0 / (h h0)
@@ -91,6 +92,7 @@ struct SysSWE {
 struct SysAdvDiff {
     static constexpr int K = 3, D = 2, id = 0;
     static constexpr bool precise = true;    // float-float equilibrium in single precision
+    static constexpr bool compensated = true;   // two-sum moments dQ = hi + lo
     static constexpr bool tracker(int k) { return k > 0; }
 
     template <class S, class R>
@@ -134,6 +136,7 @@ struct SysAdvDiff {
 struct SysNeoHooke {
     static constexpr int K = 6, D = 2, id = 2;
     static constexpr bool precise = true;    // float-float equilibrium in single precision
+    static constexpr bool compensated = true;   // two-sum moments dQ = hi + lo
     static constexpr bool tracker(int) { return false; }
 
     template <class S, class R>
@@ -235,6 +238,7 @@ struct SysNeoHooke {
 struct SysNSF17 {
     static constexpr int K = 17, D = 3, id = 3;
     static constexpr bool precise = false;   // plain exact-moment equilibrium (VALU budget)
+    static constexpr bool compensated = true;   // two-sum moments dQ = hi + lo
     static constexpr bool tracker(int k) { return k >= 5; }
 
     template <class S, class R>

@@ -17,9 +17,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_lib", "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOTBOUND, LBM_EHIP, LBM_ESUBCHAR, LBM_ENONFINITE = 0, -1, -2, -3, -4, -5
-F64, F32, F16 = 0, 1, 2
+F64, F32, F16, F16NE = 0, 1, 2, 3
 RED_SUMS, RED_RELL2, RED_RELLINF, RED_MAXSPEED, RED_NONFINITE = 0, 1, 2, 3, 4
-STORAGE = {"f64": F64, "f32": F32, "f16": F16}
+STORAGE = {"f64": F64, "f32": F32, "f16": F16, "f16ne": F16NE}
 
 EXPORTS = ["lbm_create", "lbm_last_error", "lbm_num_fields", "lbm_num_velocities", "lbm_set_param", "lbm_get_param",
            "lbm_set_storage", "lbm_set_reference", "lbm_get_reference", "lbm_required_bytes", "lbm_bind",

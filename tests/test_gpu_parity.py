@@ -163,7 +163,8 @@ F16_V_XFAIL = pytest.mark.xfail(
            "its own norm after 2000 steps, above 1e-3; the deformation gradient is at 1.3e-4", strict=False)
 
 
-@pytest.mark.parametrize("storage,tol", [("f32", 1e-6), pytest.param("f16", 1e-3, marks=F16_V_XFAIL)])
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-6), pytest.param("f16", 1e-3, marks=F16_V_XFAIL),
+                                         ("f16ne", 1e-3)])
 def test_neohooke_matches_oracle(storage, tol):
     """C5 at its parity grid 256^2 for the full 2000 steps."""
     print(f"neohooke2d D2Q9 {storage} 256x256 2000 steps", flush=True)
@@ -215,3 +216,24 @@ def test_checkpoint_restart_is_bit_identical():
     assert c.steps == 50
     c.step(50)
     assert np.array_equal(c.moments().cpu().numpy(), full)
+
+
+@pytest.mark.parametrize("storage", ["f16", "f16ne"])
+def test_fp16_initialisation_reproduces_fields(storage):
+    """Right after the equilibrium initialisation the moments equal the input
+    fields up to the binary16 rounding of the stored values."""
+    p = inputs.PRESETS["neohooke2048"]
+    g = lbm.from_preset(p, n=128, storage=storage)
+    Q = inputs.neohooke_initial(128)
+    g.init(Q)
+    M = g.moments().cpu().numpy()
+    assert rel(M[:4], Q[:4]) < 1e-4
+    assert np.abs(M[4:]).max() < 1e-5
+
+
+def test_swe_f16ne_matches_oracle():
+    print("swe2d D2Q9 f16ne 256x256 1000 steps", flush=True)
+    Qg, Qo, _, _ = _swe_pair(256, 256, 1000, storage="f16ne", with_b=True)
+    eh, em = rel(Qg[0], Qo[0]), rel(Qg[1:], Qo[1:])
+    print(f"rel L2 h {eh:.3e} hu {em:.3e}")
+    assert eh <= 1e-3 and em <= 1e-3
