@@ -86,7 +86,7 @@ def cpu_baseline(target_s=10.0):
     t = time.perf_counter()
     o.step(1)
     one = time.perf_counter() - t
-    n = max(1, min(200, int(target_s / max(one, 1e-3))))
+    n = max(1, min(5000, int(target_s / max(one, 1e-3))))
     t = time.perf_counter()
     o.step(n)
     dt = time.perf_counter() - t
