@@ -144,6 +144,26 @@ def probe_peak(torch, lbm):
     return round(2 * n / ms / 1e6, 1)
 
 
+def probe_pattern(torch, lbm, n, fields=3, reps=20):
+    """The D2Q9 step's memory-access pattern without arithmetic at n x n
+    (9 fields float planes pulled and stored): GB/s of 2 x 36 fields n^2 bytes."""
+    nbytes = 36 * fields * n * n
+    a = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    for _ in range(3):
+        lbm.bw_streams(b, a, n, n, fields)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        lbm.bw_streams(b, a, n, n, fields)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return round(2 * nbytes / ms / 1e6, 1)
+
+
 def extra_runs(torch, lbm, inputs):
     out = {}
 
@@ -246,6 +266,11 @@ def main():
     if not args.no_extra:
         line.update(adjoint_ratio(torch))
         line["probe_peak_GBps"] = probe_peak(torch, lbm)
+        # the step's own access pattern (27 pulled + 27 stored float planes)
+        # without arithmetic, at the benchmark grid and at 2048^2 (HBM-resident)
+        pat = {"swe1024": probe_pattern(torch, lbm, 1024), "swe2048": probe_pattern(torch, lbm, 2048)}
+        line["probe_pattern_GBps"] = pat
+        line["roofline"]["frac_of_pattern_probe"] = round(achieved / pat["swe1024"], 4)
         line["extra"] = extra_runs(torch, lbm, inputs)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()

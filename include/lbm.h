@@ -22,7 +22,9 @@
  *  - Every device pointer is memory the caller owns (e.g. a torch tensor);
  *    the library never allocates or frees device memory.
  *  - Layouts are structure-of-arrays with x fastest: a field array is
- *    [K][nz][ny][nx], a population array [K][Q][nz][ny][nx].
+ *    [K][nz][ny][nx], a population array [nz][K][Q][ny][nx] (z-slab major,
+ *    so that one slab's populations are contiguous; for 2D grids, nz = 1,
+ *    this is [K][Q][ny][nx]).
  *  - Population order: D2Q5 = rest, +x, +y, -x, -y; D2Q9 = D2Q5 then
  *    (+1,+1), (-1,+1), (-1,-1), (+1,-1); D3Q7 = rest, +x, -x, +y, -y, +z, -z.
  *  - Calls are asynchronous on the bound HIP stream unless they return host
@@ -210,9 +212,23 @@ int lbm_load(lbm_state *h, const void *host_buf, size_t n);
 int lbm_snapshot(lbm_state *h, void *dev_buf);
 int lbm_restore(lbm_state *h, const void *dev_buf, long long step);
 
-/* Streaming-bandwidth probe: copies n bytes src -> dst with the same
- * launch shape as the stepper (the measured-peak denominator). */
+/* Bandwidth probes (measurement only; no part of a step).
+ *
+ * lbm_bw_copy copies n bytes src -> dst, 16 bytes per lane with
+ * non-temporal loads and stores: the best plain-copy rate of the part.
+ *
+ * lbm_bw_streams reproduces the memory-access pattern of the 2D D2Q9 step
+ * without its arithmetic: src and dst each hold 9 * fields float planes of
+ * nx * ny cells ([fields][9][ny][nx], byte size 36 fields nx ny); every
+ * cell (x, y) reads plane j at the periodic pull position (x, y) - c_(j mod 9)
+ * (D2Q9 order of the population layout) and writes it to plane j at (x, y),
+ * one 4-byte element per lane and plane, all loads of a cell issued before
+ * its stores.  fields must be 3 or 6; LBM_EINVAL otherwise or for null
+ * pointers or nx, ny < 1.  Asynchronous on hip_stream.  With the step's
+ * own sizes it measures what the memory system delivers for that access
+ * pattern. */
 int lbm_bw_copy(void *dst, const void *src, size_t n, void *hip_stream);
+int lbm_bw_streams(void *dst, const void *src, int nx, int ny, int fields, void *hip_stream);
 
 /* Release the handle (does not touch bound buffers). */
 void lbm_destroy(lbm_state *h);

@@ -83,6 +83,18 @@ __device__ inline void cell_coords(I cell, int nx, int ny, int &x, int &y, int &
 }
 
 // ------------------------------------------------------- addressing ----
+// Population layout [nz][K][Q][ny][nx]: z-slab major, so that the K Q
+// population planes of one slab are contiguous and a wave's loads and
+// stores touch a few pages instead of K Q planes far apart (the per-CU
+// address-translation cache would otherwise miss).  For 2D grids this is
+// [K][Q][cells].  Element of population (k, i) stored at cell c = z P + yx:
+template <int K, int Q>
+__device__ inline size_t pop_at(int k, int i, long long c, long long P)
+{
+    const long long z = c / P;
+    return ((size_t)(z * K + k) * Q + i) * (size_t)P + (size_t)(c - z * P);
+}
+
 // Population buffers are [K][Q][cells].  A thread reaches field k through
 // the wave-uniform base of that field's [Q][cells] block (kept in scalar
 // registers) plus a per-lane byte offset.  When a block is below 4 GiB the

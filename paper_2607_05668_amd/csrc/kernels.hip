@@ -148,27 +148,38 @@ __global__ __launch_bounds__(step_block<Sys>()) void k_step(const St *__restrict
     using R = typename Store<St>::R;
     using I = typename Index<O32>::T;
     constexpr int K = Sys::K, Q = Lat::Q, D = Lat::D;
+    constexpr int B = step_block<Sys>();
     constexpr I S = sizeof(St);
-    const I cell = (I)xcd_tile(blockIdx.x, gridDim.x) * step_block<Sys>() + threadIdx.x;
-    if (cell >= (I)p.C) return;
-    int x, y, z;
-    cell_coords(cell, p.nx, p.ny, x, y, z);
-    // byte offsets inside one field's [Q][cells] block: pulled population i
-    // and this cell's slot of population i
-    const I C = (I)p.C;
+    // Tiles never straddle two z-planes: tile t covers the in-plane indices
+    // [tp B, tp B + B) of plane z = t / tpp (tpp tiles per plane), so z and
+    // the slab bases are uniform over the workgroup.
+    const I P = (I)p.nx * (I)p.ny;
+    const unsigned tpp = (unsigned)((P + B - 1) / B);
+    const unsigned t = (unsigned)xcd_tile(blockIdx.x, gridDim.x);
+    const int z = (int)(t / tpp);
+    const I yx = (I)(t - (unsigned)z * tpp) * B + threadIdx.x;
+    if (yx >= P) return;
+    const I cell = (I)z * P + yx;
+    const int y = (int)(yx / (I)p.nx), x = (int)(yx - (I)y * (I)p.nx);
+    // byte offsets inside one (slab, field) block [Q][ny][nx]: the pulled
+    // population i comes from in-plane index src and slab zs
     I src[Q];
-    neighbours<Lat>(x, y, z, p.nx, p.ny, p.nz, -1, src);
+    int zs[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) src[i] = ((I)i * C + src[i]) * S;
-    const I own = cell * S;
-    const size_t field = (size_t)Q * p.C;      // elements per field block
+    for (int i = 0; i < Q; ++i) {
+        const int xs = wrapi(x - Lat::cx[i], p.nx), ys = wrapi(y - Lat::cy[i], p.ny);
+        zs[i] = D == 3 ? wrapi(z - Lat::cz[i], p.nz) : 0;
+        src[i] = ((I)i * P + (I)ys * (I)p.nx + (I)xs) * S;
+    }
+    const I own = yx * S;
+    const size_t blk = (size_t)Q * (size_t)P;     // elements per (slab, field) block
 
     R f[K][Q];
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const R v = Store<St>::ld(byte_at(fin + k * field, src[i]));
+            const R v = Store<St>::ld(byte_at(fin + ((size_t)zs[i] * K + k) * blk, src[i]));
             if constexpr (std::is_same<St, _Float16>::value)
                 f[k][i] = v * (R)p.inv_scale[k];
             else
@@ -276,7 +287,7 @@ __global__ __launch_bounds__(step_block<Sys>()) void k_step(const St *__restrict
                 post = eh[i] + (fma(c1, eh[i] - fi, c2 * el[i]) + s[i]);
             else
                 post = fma(c1, eh[i] - fi, eh[i]) + s[i];
-            St *dst = byte_at(fout + k * field, (I)i * C * S + own);
+            St *dst = byte_at(fout + ((size_t)z * K + k) * blk, (I)i * P * S + own);
             if constexpr (std::is_same<St, _Float16>::value) {
                 const _Float16 hv = (_Float16)(post * (R)p.scale[k]);
                 st_pop<NT>(dst, hv);
@@ -288,7 +299,7 @@ __global__ __launch_bounds__(step_block<Sys>()) void k_step(const St *__restrict
         }
         R rest = f[k][0] + acc;
         if constexpr (std::is_same<St, _Float16>::value) rest *= (R)p.scale[k];
-        Store<St>::template st<NT>(byte_at(fout + k * field, own), rest);
+        Store<St>::template st<NT>(byte_at(fout + ((size_t)z * K + k) * blk, own), rest);
     }
     if constexpr (REC) {
 #pragma unroll
@@ -323,7 +334,7 @@ __global__ __launch_bounds__(kBlock) void k_init(const double *__restrict__ Qin,
 #pragma unroll
             for (int a = 0; a < D; ++a) cd += lat_c<Lat>(i, a) * dPhi[k][a];
             const double feq = Lat::w[i] * (dQ[k] + p.lam_cs2 * cd);
-            Store<St>::st_init(fout + (size_t)(k * Q + i) * C + dst[i], feq * (double)p.scale[k]);
+            Store<St>::st_init(fout + pop_at<K, Q>(k, i, dst[i], (long long)p.nx * p.ny), feq * (double)p.scale[k]);
         }
 }
 
@@ -378,7 +389,8 @@ __global__ __launch_bounds__(kBlock) void k_moments(const St *__restrict__ fin, 
     for (int k = 0; k < K; ++k) {
         double s = 0.0;
 #pragma unroll
-        for (int i = 0; i < Q; ++i) s += (double)Store<St>::ld(fin + (size_t)(k * Q + i) * C + src[i]);
+        for (int i = 0; i < Q; ++i)
+            s += (double)Store<St>::ld(fin + pop_at<K, Q>(k, i, src[i], (long long)p.nx * p.ny));
         s *= (double)p.inv_scale[k];
         out[(size_t)k * C + cell] = (Out)(absolute ? s + p.phys.Q0[k] : s);
     }
@@ -420,7 +432,8 @@ __global__ __launch_bounds__(kBlock) void k_reduce1(const St *__restrict__ fin, 
         for (int k = 0; k < K; ++k) {
             double s = 0.0;
 #pragma unroll
-            for (int i = 0; i < Q; ++i) s += (double)Store<St>::ld(fin + (size_t)(k * Q + i) * C + src[i]);
+            for (int i = 0; i < Q; ++i)
+                s += (double)Store<St>::ld(fin + pop_at<K, Q>(k, i, src[i], (long long)p.nx * p.ny));
             q[k] = s * (double)p.inv_scale[k] + p.phys.Q0[k];
         }
         if (what == 0) {
@@ -652,6 +665,41 @@ hipError_t lbm_launch_copy(void *dst, const void *src, size_t n, hipStream_t s)
     return hipGetLastError();
 }
 
+// The D2Q9 step's memory pattern without arithmetic: N = 9 fields planes,
+// plane j pulled from (x, y) - c_(j mod 9), periodic, and stored at (x, y).
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_streams(const float *__restrict__ src, float *__restrict__ dst, int nx,
+                                                    int ny)
+{
+    const unsigned P = (unsigned)nx * (unsigned)ny;
+    const unsigned c = (unsigned)xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (c >= P) return;
+    const int y = (int)(c / (unsigned)nx), x = (int)(c - (unsigned)y * nx);
+    float v[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const int i = j % 9;
+        const unsigned s = (unsigned)wrapi(y - D2Q9::cy[i], ny) * nx + (unsigned)wrapi(x - D2Q9::cx[i], nx);
+        v[j] = *byte_at(src + (size_t)j * P, s * 4u);
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) *byte_at(dst + (size_t)j * P, c * 4u) = v[j];
+}
+
+hipError_t lbm_launch_streams(void *dst, const void *src, int nx, int ny, int fields, hipStream_t s)
+{
+    const size_t P = (size_t)nx * ny;
+    if (P * 4 > 0xffffffffull) return hipErrorInvalidValue;     // 32-bit byte offsets per plane
+    const dim3 grid((unsigned)((P + kBlock - 1) / kBlock));
+    if (fields == 3)
+        hipLaunchKernelGGL(k_streams<27>, grid, dim3(kBlock), 0, s, (const float *)src, (float *)dst, nx, ny);
+    else if (fields == 6)
+        hipLaunchKernelGGL(k_streams<54>, grid, dim3(kBlock), 0, s, (const float *)src, (float *)dst, nx, ny);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------- host: params ----
 template <class R>
 KParams<R> lbm_state_impl::kparams(double t_half) const
@@ -762,15 +810,17 @@ struct Impl {
                             const KParams<R> &p)
     {
         constexpr int B = step_block<Sys>();
-        hipLaunchKernelGGL((k_step<Sys, Lat, St, REC, NT, O32>), dim3((unsigned)((h.C + B - 1) / B)), dim3(B), 0,
-                           s, (const St *)fin, (St *)fout, p, (R *)qhist);
+        const long long tpp = ((long long)h.nx * h.ny + B - 1) / B;    // tiles per z-plane
+        hipLaunchKernelGGL((k_step<Sys, Lat, St, REC, NT, O32>), dim3((unsigned)(tpp * h.nz)), dim3(B), 0, s,
+                           (const St *)fin, (St *)fout, p, (R *)qhist);
     }
     template <bool REC, bool NT>
     static void launch_step(const lbm_state_impl &h, const void *fin, void *fout, void *qhist, hipStream_t s,
                             const KParams<R> &p)
     {
-        // the 32-bit form also needs the history and source planes in range
-        if (fits_o32(h.C, Lat::Q, sizeof(St)) && fits_o32(h.C, 1, sizeof(R)))
+        // the 32-bit form needs one (slab, field) block and the history and
+        // source planes below 4 GiB
+        if (fits_o32((long long)h.nx * h.ny, Lat::Q, sizeof(St)) && fits_o32(h.C, 1, sizeof(R)))
             launch_step<REC, NT, true>(h, fin, fout, qhist, s, p);
         else
             launch_step<REC, NT, false>(h, fin, fout, qhist, s, p);

@@ -62,21 +62,73 @@ __device__ inline void ne_load(const _Float16 *__restrict__ g, const float *__re
     }
 }
 
+// The step works on a tile of kNeTX x kNeTY cells whose senders (the tile
+// and a one-cell halo, periodic) first put their stored moments and
+// lam dPhi(M) into LDS: the flux of each sender is evaluated once per
+// workgroup instead of once per pulled population (Q - 1 times per cell).
+// The receiver then rebuilds each pulled population from LDS with the same
+// float operations as the sender-side definition above.
+constexpr int kNeTX = 64, kNeTY = 4;
+
+__device__ inline int pmod(int v, int n)
+{
+    const int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
 template <class Sys, class Lat, bool NT>
-__global__ __launch_bounds__(kBlock) void k_step_ne(const _Float16 *__restrict__ gin, const float *__restrict__ Min,
-                                                    _Float16 *__restrict__ gout, float *__restrict__ Mout,
-                                                    const KParams<float> p)
+__global__ __launch_bounds__(kNeTX * kNeTY) void k_step_ne(const _Float16 *__restrict__ gin,
+                                                           const float *__restrict__ Min,
+                                                           _Float16 *__restrict__ gout, float *__restrict__ Mout,
+                                                           const KParams<float> p)
 {
     constexpr int K = Sys::K, Q = Lat::Q, D = Lat::D;
-    const long long cell = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (cell >= p.C) return;
-    int x, y, z;
-    cell_coords(cell, p.nx, p.ny, x, y, z);
-    long long src[Q];
-    neighbours<Lat>(x, y, z, p.nx, p.ny, p.nz, -1, src);
+    constexpr int HX = kNeTX + 2, HY = kNeTY + 2, NH = HX * HY, NTH = kNeTX * kNeTY;
+    __shared__ float sM[K][NH];
+    __shared__ float sG[K][D][NH];
     const size_t C = (size_t)p.C;
+    const int tilesx = (p.nx + kNeTX - 1) / kNeTX;
+    const unsigned t = (unsigned)xcd_tile(blockIdx.x, gridDim.x);
+    const int tx0 = (int)(t % (unsigned)tilesx) * kNeTX, ty0 = (int)(t / (unsigned)tilesx) * kNeTY;
+    for (int h = threadIdx.x; h < NH; h += NTH) {
+        const int hy = h / HX, hx = h - hy * HX;
+        const size_t c = (size_t)pmod(ty0 + hy - 1, p.ny) * p.nx + pmod(tx0 + hx - 1, p.nx);
+        float My[K], P[K][D];
+#pragma unroll
+        for (int k = 0; k < K; ++k) My[k] = Min[(size_t)k * C + c];
+        Sys::template flux_delta<float, float>(p.phys, My, P);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            sM[k][h] = My[k];
+#pragma unroll
+            for (int a = 0; a < D; ++a) sG[k][a][h] = p.lam * P[k][a];
+        }
+    }
+    __syncthreads();
+    const int lx = (int)threadIdx.x % kNeTX, ly = (int)threadIdx.x / kNeTX;
+    const int x = tx0 + lx, y = ty0 + ly;
+    if (x >= p.nx || y >= p.ny) return;                 // no barrier follows
+    const long long cell = (long long)y * p.nx + x;
     float f[K][Q];
-    ne_load<Sys, Lat>(gin, Min, p, src, f);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const size_t src = (size_t)wrapi(y - Lat::cy[i], p.ny) * p.nx + wrapi(x - Lat::cx[i], p.nx);
+        const int h = (ly + 1 - Lat::cy[i]) * HX + (lx + 1 - Lat::cx[i]);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            float ei;
+            if (i == 0) {
+                ei = ExactEq<Lat>::rest(sM[k][h]);
+            } else {
+                float G[D], e[Q];
+#pragma unroll
+                for (int a = 0; a < D; ++a) G[a] = sG[k][a][h];
+                ExactEq<Lat>::feq(sM[k][h], 0.0f, G, e);
+                ei = e[i];
+            }
+            f[k][i] = (float)gin[(size_t)(k * Q + i) * C + src] * p.inv_scale[k] + ei;
+        }
+    }
     float dQ[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -309,6 +361,10 @@ __global__ __launch_bounds__(kBlock) void k_reduce2_ne(const double *__restrict_
 template <class Sys, class Lat>
 struct ImplNE {
     static unsigned grid(long long C) { return (unsigned)((C + kBlock - 1) / kBlock); }
+    static unsigned step_grid(const lbm_state_impl &h)
+    {
+        return (unsigned)(((h.nx + kNeTX - 1) / kNeTX) * (long long)((h.ny + kNeTY - 1) / kNeTY));
+    }
     static const _Float16 *gp(const lbm_state_impl &, const void *buf) { return (const _Float16 *)buf; }
     static const float *mp(const lbm_state_impl &h, const void *buf)
     {
@@ -321,10 +377,10 @@ struct ImplNE {
         const KParams<float> p = h.kparams<float>(h.t0 + (h.nsteps + 0.5) * h.dt);
         const bool nt = 2 * (ne_pop_bytes(h.C, Sys::K, Lat::Q) + (size_t)Sys::K * h.C * 4) > kLastLevelCacheBytes;
         if (nt)
-            hipLaunchKernelGGL((k_step_ne<Sys, Lat, true>), dim3(grid(h.C)), dim3(kBlock), 0, s, gp(h, fin),
+            hipLaunchKernelGGL((k_step_ne<Sys, Lat, true>), dim3(step_grid(h)), dim3(kNeTX * kNeTY), 0, s, gp(h, fin),
                                mp(h, fin), (_Float16 *)fout, (float *)mp(h, fout), p);
         else
-            hipLaunchKernelGGL((k_step_ne<Sys, Lat, false>), dim3(grid(h.C)), dim3(kBlock), 0, s, gp(h, fin),
+            hipLaunchKernelGGL((k_step_ne<Sys, Lat, false>), dim3(step_grid(h)), dim3(kNeTX * kNeTY), 0, s, gp(h, fin),
                                mp(h, fin), (_Float16 *)fout, (float *)mp(h, fout), p);
         return hipGetLastError();
     }

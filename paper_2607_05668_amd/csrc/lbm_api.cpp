@@ -563,6 +563,12 @@ int lbm_bw_copy(void *dst, const void *src, size_t n, void *hip_stream)
     return lbm_launch_copy(dst, src, n, (hipStream_t)hip_stream) == hipSuccess ? LBM_OK : LBM_EHIP;
 }
 
+int lbm_bw_streams(void *dst, const void *src, int nx, int ny, int fields, void *hip_stream)
+{
+    if (!dst || !src || nx < 1 || ny < 1 || (fields != 3 && fields != 6)) return LBM_EINVAL;
+    return lbm_launch_streams(dst, src, nx, ny, fields, (hipStream_t)hip_stream) == hipSuccess ? LBM_OK : LBM_EHIP;
+}
+
 void lbm_destroy(lbm_state *h) { delete h; }
 
 }  // extern "C"

@@ -25,7 +25,8 @@ EXPORTS = ["lbm_create", "lbm_last_error", "lbm_num_fields", "lbm_num_velocities
            "lbm_set_storage", "lbm_set_reference", "lbm_get_reference", "lbm_required_bytes", "lbm_bind",
            "lbm_set_field", "lbm_init_moments", "lbm_step", "lbm_step_record", "lbm_moments", "lbm_reduce",
            "lbm_step_count", "lbm_time", "lbm_adjoint_seed", "lbm_adjoint_step", "lbm_adjoint_to_initial",
-           "lbm_save", "lbm_load", "lbm_snapshot", "lbm_restore", "lbm_bw_copy", "lbm_destroy"]
+           "lbm_save", "lbm_load", "lbm_snapshot", "lbm_restore", "lbm_bw_copy", "lbm_bw_streams",
+           "lbm_destroy"]
 
 
 class LbmError(RuntimeError):
@@ -79,6 +80,7 @@ def load_library():
     lib.lbm_snapshot.argtypes = [vp, vp]
     lib.lbm_restore.argtypes = [vp, vp, ctypes.c_longlong]
     lib.lbm_bw_copy.argtypes = [vp, vp, c_size, vp]
+    lib.lbm_bw_streams.argtypes = [vp, vp, c_int, c_int, c_int, vp]
     lib.lbm_destroy.restype = None
     lib.lbm_destroy.argtypes = [vp]
     _lib = lib
@@ -284,9 +286,27 @@ def from_preset(preset, n=None, storage=None, params=None, reference=None, tau_r
                    reference=reference)
 
 
-def bw_copy(dst, src, nbytes, stream=None):
+def bw_streams(dst, src, nx, ny, fields, stream=None):
+    """D2Q9 step memory-pattern probe: 9 fields planes of nx*ny floats pulled
+    at the lattice offsets and stored (no arithmetic); see include/lbm.h."""
     lib = load_library()
     torch = _torch()
+    need = 36 * fields * nx * ny
+    if dst.numel() * dst.element_size() < need or src.numel() * src.element_size() < need:
+        raise ValueError(f"bw_streams needs {need} bytes per buffer")
+    s = stream or torch.cuda.current_stream()
+    rc = lib.lbm_bw_streams(dst.data_ptr(), src.data_ptr(), int(nx), int(ny), int(fields),
+                            ctypes.c_void_p(s.cuda_stream))
+    if rc != LBM_OK:
+        raise LbmError(rc, "bw_streams failed")
+
+
+def bw_copy(dst, src, nbytes, stream=None):
+    """Copy probe: nbytes from src to dst (16-byte non-temporal lanes)."""
+    lib = load_library()
+    torch = _torch()
+    if dst.numel() * dst.element_size() < nbytes or src.numel() * src.element_size() < nbytes:
+        raise ValueError(f"bw_copy needs {nbytes} bytes per buffer")
     s = stream or torch.cuda.current_stream()
     rc = lib.lbm_bw_copy(dst.data_ptr(), src.data_ptr(), int(nbytes), ctypes.c_void_p(s.cuda_stream))
     if rc != LBM_OK:

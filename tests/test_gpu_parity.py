@@ -237,3 +237,16 @@ def test_swe_f16ne_matches_oracle():
     eh, em = rel(Qg[0], Qo[0]), rel(Qg[1:], Qo[1:])
     print(f"rel L2 h {eh:.3e} hu {em:.3e}")
     assert eh <= 1e-3 and em <= 1e-3
+
+
+@pytest.mark.parametrize("shape", [(37, 100), (5, 24), (4, 64)])
+def test_swe_f16ne_ragged_tiles_match_oracle(shape):
+    """F16NE works on 64 x 4 cell tiles with a one-cell periodic halo: partial
+    tiles in x and y, and grids narrower than one tile (the halo wraps more
+    than once), against the oracle."""
+    ny, nx = shape
+    print(f"swe2d D2Q9 f16ne {nx}x{ny} 300 steps", flush=True)
+    Qg, Qo, _, _ = _swe_pair(nx, ny, 300, storage="f16ne", with_b=True)
+    eh, em = rel(Qg[0], Qo[0]), rel(Qg[1:], Qo[1:])
+    print(f"rel L2 h {eh:.3e} hu {em:.3e}")
+    assert eh <= 1e-3 and em <= 1e-3
