@@ -756,6 +756,11 @@ KParams<R> lbm_state_impl::kparams(double t_half) const
             for (int b = 0; b < 3; ++b)
                 d.tau_ref[3 * a + b] = mu * (Q0[5 + 3 * a + b] + Q0[5 + 3 * b + a] - (a == b ? 2.0 / 3.0 * trG : 0.0));
     }
+    if (sys == SYS_SWE) {
+        d.mm0_h0[0] = Q0[1] * Q0[1] / Q0[0];
+        d.mm0_h0[1] = Q0[1] * Q0[2] / Q0[0];
+        d.mm0_h0[2] = Q0[2] * Q0[2] / Q0[0];
+    }
     if (sys == SYS_NEOHOOKE) {
         double H[4] = {Q0[0] - 1.0, Q0[1], Q0[2], Q0[3] - 1.0}, P[4];
         for (int j = 0; j < 4; ++j) d.H0[j] = H[j];
@@ -765,6 +770,7 @@ KParams<R> lbm_state_impl::kparams(double t_half) const
     // convert
     for (int k = 0; k < LBM_MAXK; ++k) p.phys.Q0[k] = (R)d.Q0[k];
     p.phys.g = (R)d.g;
+    for (int j = 0; j < 3; ++j) p.phys.mm0_h0[j] = (R)d.mm0_h0[j];
     for (int a = 0; a < 3; ++a) {
         p.phys.a[a] = (R)d.a[a];
         p.phys.u_ref[a] = (R)d.u_ref[a];

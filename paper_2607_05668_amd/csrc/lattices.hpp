@@ -163,13 +163,13 @@ __host__ __device__ inline FF<R> ff_add(FF<R> a, FF<R> b)
 
 // (hi + lo) / (B P) for B = 3 or 9 and a power of two P: q = RN(hi / (B P)),
 // the remainder hi - q B P is exact, and the low part (r + lo) / (B P) needs
-// no correct rounding.
+// no correct rounding (a product with the rounded reciprocal).
 template <int B, class R>
 __host__ __device__ inline FF<R> ff_div(R hi, R lo, R P)
 {
     const R q = div_by<B>(hi) / P;
     const R r = fma(-q, R(B) * P, hi);
-    return {q, div_by<B>(r + lo) / P};
+    return {q, (r + lo) * (R(1) / (R(B) * P))};
 }
 
 template <class R>

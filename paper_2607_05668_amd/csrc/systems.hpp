@@ -22,6 +22,7 @@ template <class R>
 struct Phys {
     R Q0[LBM_MAXK];       // reference state
     R g;                  // SWE gravity
+    R mm0_h0[3];          // SWE m0_a m0_b / h0 for (x,x), (x,y), (y,y)
     R a[3], nu, react;    // advection velocity, diffusivity, reaction rate
     R inv_tau_grad;       // 1 / tau_grad, tau_grad = g_tau dt
     R gamma, mu, kappa;   // NSF
@@ -42,11 +43,12 @@ struct SysSWE {
     static constexpr bool compensated = true;   // two-sum moments dQ = hi + lo
     static constexpr bool tracker(int) { return false; }
 
-    // d(a b / h) = (a0 db + b0 da + da db)/h - dh a0 b0 / (h h0)
+    // d(a b / h) = ((a0 db + b0 da + da db) - dh a0 b0 / h0) / h, with the
+    // reference ratio q0 = a0 b0 / h0 formed on the host
     template <class S, class R>
-    __host__ __device__ static S dprod(R a0, R b0, const S &da, const S &db, const S &h, R h0, const S &dh)
+    __host__ __device__ static S dprod(R a0, R b0, R q0, const S &da, const S &db, const S &h, const S &dh)
     {
-        return (a0 * db + b0 * da + da * db) / h - dh * (a0 * b0 / h0) / h;
+        return ((a0 * db + b0 * da + da * db) - dh * q0) / h;
     }
 
     template <class S, class R>
@@ -56,13 +58,13 @@ struct SysSWE {
         const S dh = dQ[0], dmx = dQ[1], dmy = dQ[2];
         const S h = dh + h0;
         const S pres = p.g * dh * (dh * R(0.5) + h0);          // g (h^2 - h0^2) / 2
-        const S xy = dprod(mx0, my0, dmx, dmy, h, h0, dh);
+        const S xy = dprod(mx0, my0, p.mm0_h0[1], dmx, dmy, h, dh);
         dPhi[0][0] = dmx;
         dPhi[0][1] = dmy;
-        dPhi[1][0] = pres + dprod(mx0, mx0, dmx, dmx, h, h0, dh);
+        dPhi[1][0] = pres + dprod(mx0, mx0, p.mm0_h0[0], dmx, dmx, h, dh);
         dPhi[1][1] = xy;
         dPhi[2][0] = xy;
-        dPhi[2][1] = pres + dprod(my0, my0, dmy, dmy, h, h0, dh);
+        dPhi[2][1] = pres + dprod(my0, my0, p.mm0_h0[2], dmy, dmy, h, dh);
     }
 
     template <class S, class R>
