@@ -32,7 +32,7 @@
 #define MAXK 17
 #define MAXQ 9
 
-enum { SYS_ADVDIFF = 0, SYS_SWE = 1, SYS_NEOHOOKE = 2, SYS_NSF17 = 3 };
+enum { SYS_ADVDIFF = 0, SYS_SWE = 1, SYS_NEOHOOKE = 2, SYS_NSF17 = 3, SYS_BURGERS = 4, SYS_EULER = 5 };
 enum { LAT_D2Q5 = 0, LAT_D2Q9 = 1, LAT_D3Q7 = 2 };
 enum {
     P_G = 0, P_AX, P_AY, P_AZ, P_NU, P_R, P_TAUG, P_GAMMA, P_MU, P_KAPPA,
@@ -98,6 +98,8 @@ static int system_K(int sys)
     case SYS_SWE: return 3;
     case SYS_NEOHOOKE: return 6;
     case SYS_NSF17: return 17;
+    case SYS_BURGERS: return 1;
+    case SYS_EULER: return 4;
     }
     return 0;
 }

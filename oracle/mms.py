@@ -17,6 +17,9 @@ Cases:
   (supplement, ADR MMS), with the tracker initialised at grad c.
 * ``neohooke_paper`` -- the paper's finite-strain elasticity MMS
   (supplement, elasticity MMS) with mu_s/rho0 = 1, lambda_s/rho0 = 2.
+* ``burgers_paper`` -- the paper's inviscid-Burgers MMS (amplitude 1.3).
+* ``euler_paper`` -- the paper's compressible-Euler MMS, nondimensional
+  (rho0 = 1, cs = 1: background Mach 3 per axis).
 * ``nsf17``      -- the 3D compressible NSF manufactured solution with the
   shapes of the paper's homogenized-NSF MMS (porosity 1), conserved rows
   forced; tracker rows are forced only when ``force_trackers`` is set.
@@ -79,6 +82,53 @@ def adr_paper(u0=0.1, u1=-0.1, D=0.01, R=1.0, tau_grad=None):
     res_c = sp.diff(c, T) + _div(Phi_c, (X, Y)) - S_c
     fQ = sp.lambdify((X, Y, T), [c, gx, gy], "numpy")
     fS = sp.lambdify((X, Y, T), [res_c, sp.Integer(0), sp.Integer(0)], "numpy", cse=True)
+    return _wrap2(fQ), _wrap2(fS)
+
+
+# ------------------------------------------------------------ BURGERS ----
+@functools.lru_cache(maxsize=None)
+def burgers_paper(amp=1.3):
+    """The paper's inviscid-Burgers MMS (supplement, Burgers MMS):
+    u = A sin(2 pi x) sin(2 pi y) cos t with A = 1.3, flux (u^2/2, u^2/2)."""
+    A = sp.Float(amp)
+    u = A * sp.sin(PI2 * X) * sp.sin(PI2 * Y) * sp.cos(T)
+    res = sp.diff(u, T) + sp.diff(u ** 2 / 2, X) + sp.diff(u ** 2 / 2, Y)
+    fQ = sp.lambdify((X, Y, T), [u], "numpy")
+    fS = sp.lambdify((X, Y, T), [res], "numpy", cse=True)
+    return _wrap2(fQ), _wrap2(fS)
+
+
+# -------------------------------------------------------------- EULER ----
+def euler_exact_exprs(rho0=1.0, cs=1.0, gamma=1.4):
+    """The paper's compressible-Euler MMS (supplement, Euler MMS): per-axis
+    Mach-3 background u0 = v0 = 3 cs, p0 = rho0 cs^2 / gamma, fluctuations
+    0.3 rho0, 0.3 cs and c_s^2 d rho + 0.2 p0 in the printed modes."""
+    r0, c, gm = sp.Float(rho0), sp.Float(cs), sp.Float(gamma)
+    p0 = r0 * c ** 2 / gm
+    drho = sp.Rational(3, 10) * r0 * sp.sin(PI2 * X) * sp.cos(PI2 * Y) * sp.cos(T)
+    du = sp.Rational(3, 10) * c * sp.cos(PI2 * X) * sp.sin(PI2 * Y) * sp.sin(T)
+    dv = sp.Rational(3, 10) * c * sp.sin(PI2 * X) * sp.sin(PI2 * Y) * sp.sin(T)
+    dp = c ** 2 * drho + sp.Rational(1, 5) * p0 * sp.cos(PI2 * X) * sp.sin(PI2 * Y) * sp.sin(T)
+    rho = r0 + drho
+    u, v = 3 * c + du, 3 * c + dv
+    p = p0 + dp
+    E = p / (gm - 1) + rho * (u ** 2 + v ** 2) / 2
+    return [rho, rho * u, rho * v, E], gm
+
+
+@functools.lru_cache(maxsize=None)
+def euler_paper(rho0=1.0, cs=1.0, gamma=1.4):
+    """(exact(x, y, t) -> [4, ...], forcing(x, y, t) -> [4, ...])."""
+    Q, gm = euler_exact_exprs(rho0, cs, gamma)
+    rho, mx, my, E = Q
+    p = (gm - 1) * (E - (mx ** 2 + my ** 2) / (2 * rho))
+    Phi = [[mx, my],
+           [mx ** 2 / rho + p, mx * my / rho],
+           [mx * my / rho, my ** 2 / rho + p],
+           [(E + p) * mx / rho, (E + p) * my / rho]]
+    res = [sp.diff(Q[k], T) + _div(Phi[k], (X, Y)) for k in range(4)]
+    fQ = sp.lambdify((X, Y, T), Q, "numpy")
+    fS = sp.lambdify((X, Y, T), res, "numpy", cse=True)
     return _wrap2(fQ), _wrap2(fS)
 
 
