@@ -183,6 +183,10 @@ def extra_runs(torch, lbm, inputs):
     one("neohooke2d_D2Q9_f16_2048", p, 2048, "f16", 200, 216, inputs.neohooke_initial(2048))
     # binary16 non-equilibrium deviations + FP32 moments: 2 (K Q 2 + K 4) bytes
     one("neohooke2d_D2Q9_f16ne_2048", p, 2048, "f16ne", 200, 264, inputs.neohooke_initial(2048))
+    p = inputs.PRESETS["burgers2048"]
+    one("burgers2d_D2Q5_f32_2048", p, 2048, "f32", 200, 40, inputs.burgers_initial(2048))
+    p = inputs.PRESETS["euler2048"]
+    one("euler2d_D2Q5_f32_2048", p, 2048, "f32", 200, 160, inputs.euler_initial(2048))
     p = inputs.PRESETS["advdiff64"]
     one("advdiff_D2Q5_f64_64", p, 64, "f64", 200, 240, inputs.advdiff_initial(64))
     p = inputs.PRESETS["nsf256"]

@@ -756,10 +756,18 @@ KParams<R> lbm_state_impl::kparams(double t_half) const
             for (int b = 0; b < 3; ++b)
                 d.tau_ref[3 * a + b] = mu * (Q0[5 + 3 * a + b] + Q0[5 + 3 * b + a] - (a == b ? 2.0 / 3.0 * trG : 0.0));
     }
-    if (sys == SYS_SWE) {
+    if (sys == SYS_SWE || sys == SYS_EULER) {
         d.mm0_h0[0] = Q0[1] * Q0[1] / Q0[0];
         d.mm0_h0[1] = Q0[1] * Q0[2] / Q0[0];
         d.mm0_h0[2] = Q0[2] * Q0[2] / Q0[0];
+    }
+    if (sys == SYS_EULER) {
+        d.p_ref = (gamma - 1.0) * (Q0[3] - 0.5 * (Q0[1] * Q0[1] + Q0[2] * Q0[2]) / Q0[0]);
+        d.H_ref = Q0[3] + d.p_ref;
+        for (int a = 0; a < 2; ++a) {
+            d.u_ref[a] = Q0[1 + a] / Q0[0];
+            d.Hu_ref[a] = d.H_ref * Q0[1 + a] / Q0[0];
+        }
     }
     if (sys == SYS_NEOHOOKE) {
         double H[4] = {Q0[0] - 1.0, Q0[1], Q0[2], Q0[3] - 1.0}, P[4];
@@ -770,7 +778,10 @@ KParams<R> lbm_state_impl::kparams(double t_half) const
     // convert
     for (int k = 0; k < LBM_MAXK; ++k) p.phys.Q0[k] = (R)d.Q0[k];
     p.phys.g = (R)d.g;
-    for (int j = 0; j < 3; ++j) p.phys.mm0_h0[j] = (R)d.mm0_h0[j];
+    for (int j = 0; j < 3; ++j) {
+        p.phys.mm0_h0[j] = (R)d.mm0_h0[j];
+        p.phys.Hu_ref[j] = (R)d.Hu_ref[j];
+    }
     for (int a = 0; a < 3; ++a) {
         p.phys.a[a] = (R)d.a[a];
         p.phys.u_ref[a] = (R)d.u_ref[a];
@@ -949,6 +960,14 @@ const Launchers *lbm_launchers(int sys, int lat, int storage)
         break;
     case SYS_NSF17:
         if (lat == LAT_D3Q7) return by_storage<SysNSF17, D3Q7>(storage);
+        break;
+    case SYS_BURGERS:
+        if (lat == LAT_D2Q5) return by_storage<SysBurgers, D2Q5>(storage);
+        if (lat == LAT_D2Q9) return by_storage<SysBurgers, D2Q9>(storage);
+        break;
+    case SYS_EULER:
+        if (lat == LAT_D2Q5) return by_storage<SysEuler, D2Q5>(storage);
+        if (lat == LAT_D2Q9) return by_storage<SysEuler, D2Q9>(storage);
         break;
     }
     return nullptr;

@@ -443,6 +443,14 @@ const Launchers *lbm_launchers_ne(int sys, int lat)
         if (lat == LAT_D2Q5) return ImplNE<SysNeoHooke, D2Q5>::get();
         if (lat == LAT_D2Q9) return ImplNE<SysNeoHooke, D2Q9>::get();
         break;
+    case SYS_BURGERS:
+        if (lat == LAT_D2Q5) return ImplNE<SysBurgers, D2Q5>::get();
+        if (lat == LAT_D2Q9) return ImplNE<SysBurgers, D2Q9>::get();
+        break;
+    case SYS_EULER:
+        if (lat == LAT_D2Q5) return ImplNE<SysEuler, D2Q5>::get();
+        if (lat == LAT_D2Q9) return ImplNE<SysEuler, D2Q9>::get();
+        break;
     }
     return nullptr;
 }

@@ -37,6 +37,8 @@ int system_id(const char *s)
     if (!std::strcmp(s, "swe2d")) return SYS_SWE;
     if (!std::strcmp(s, "neohooke2d")) return SYS_NEOHOOKE;
     if (!std::strcmp(s, "nsf3d_trk17")) return SYS_NSF17;
+    if (!std::strcmp(s, "burgers2d")) return SYS_BURGERS;
+    if (!std::strcmp(s, "euler2d")) return SYS_EULER;
     return -1;
 }
 
@@ -49,8 +51,8 @@ int lattice_id(const char *s)
     return -1;
 }
 
-const int kSysK[4] = {3, 3, 6, 17};
-const int kSysD[4] = {2, 2, 2, 3};
+const int kSysK[6] = {3, 3, 6, 17, 1, 4};
+const int kSysD[6] = {2, 2, 2, 3, 2, 2};
 const int kLatQ[3] = {5, 9, 7};
 const int kLatD[3] = {2, 2, 3};
 const double kLatCs2[3] = {1.0 / 3.0, 1.0 / 3.0, 1.0 / 4.0};
@@ -65,6 +67,18 @@ void nsf_default_reference(lbm_state *h)
     h->Q0[4] = h->mms_p0 / (h->gamma - 1.0) + 1.5 * h->mms_rho0 * h->mms_u0 * h->mms_u0;
 }
 
+// Reference state of the Euler system: the background of the paper's
+// manufactured solution in units rho0 = cs = 1 (Mach 3 per axis):
+// rho0 = 1, m0 = (3, 3), E0 = p0 / (gamma - 1) + 9 with p0 = 1 / gamma.
+void euler_default_reference(lbm_state *h)
+{
+    std::memset(h->Q0, 0, sizeof h->Q0);
+    h->Q0[0] = 1.0;
+    h->Q0[1] = 3.0;
+    h->Q0[2] = 3.0;
+    h->Q0[3] = (1.0 / h->gamma) / (h->gamma - 1.0) + 9.0;
+}
+
 void default_reference(lbm_state *h)
 {
     std::memset(h->Q0, 0, sizeof h->Q0);
@@ -73,6 +87,8 @@ void default_reference(lbm_state *h)
     case SYS_ADVDIFF: h->Q0[0] = 1.0; break;
     case SYS_NEOHOOKE: h->Q0[0] = 1.0; h->Q0[3] = 1.0; break;
     case SYS_NSF17: nsf_default_reference(h); break;
+    case SYS_BURGERS: break;                       // u0 = 0
+    case SYS_EULER: euler_default_reference(h); break;
     }
 }
 
@@ -190,6 +206,16 @@ int lbm_set_param(lbm_state *h, const char *name, double v)
         if (n == "rho0") { if (!(v > 0)) return fail(h, LBM_EINVAL, "rho0 must be positive"); h->rho0_el = v; return LBM_OK; }
         if (n == "mu_s") { h->mu_s = v; return LBM_OK; }
         if (n == "lambda_s") { h->lam_s = v; return LBM_OK; }
+        break;
+    case SYS_BURGERS:
+        break;
+    case SYS_EULER:
+        if (n == "gamma") {
+            if (!(v > 1)) return fail(h, LBM_EINVAL, "gamma must exceed 1");
+            h->gamma = v;
+            if (!h->q0_set) euler_default_reference(h);
+            return LBM_OK;
+        }
         break;
     case SYS_NSF17:
         if (n == "gamma") { if (!(v > 1)) return fail(h, LBM_EINVAL, "gamma must exceed 1"); h->gamma = v; if (!h->q0_set) nsf_default_reference(h); return LBM_OK; }

@@ -22,7 +22,8 @@ template <class R>
 struct Phys {
     R Q0[LBM_MAXK];       // reference state
     R g;                  // SWE gravity
-    R mm0_h0[3];          // SWE m0_a m0_b / h0 for (x,x), (x,y), (y,y)
+    R mm0_h0[3];          // SWE, Euler: m0_a m0_b / h0 (rho0) for (x,x), (x,y), (y,y)
+    R Hu_ref[3];          // Euler: H0 u0_a, H0 = E0 + p0
     R a[3], nu, react;    // advection velocity, diffusivity, reaction rate
     R inv_tau_grad;       // 1 / tau_grad, tau_grad = g_tau dt
     R gamma, mu, kappa;   // NSF
@@ -34,6 +35,16 @@ struct Phys {
     R P0[4];              // first Piola-Kirchhoff stress at F0
 };
 
+// d(a b / h) = ((a0 db + b0 da + da db) - dh a0 b0 / h0) / h for a = a0 + da,
+// b = b0 + db, h = h0 + dh, with the reference ratio q0 = a0 b0 / h0 formed
+// on the host: the deviation of a quotient of products without forming the
+// products themselves.
+template <class S, class R>
+__host__ __device__ inline S dquot(R a0, R b0, R q0, const S &da, const S &db, const S &h, const S &dh)
+{
+    return ((a0 * db + b0 * da + da * db) - dh * q0) / h;
+}
+
 // ------------------------------------------------------------------ SWE --
 // Shallow water (Sec. 3): Q = (h, hu, hv),
 //   Phi_h = hu, Phi_hu = hu (x) u + g h^2/2 I, S_hu = -g h grad z_b.
@@ -43,14 +54,6 @@ struct SysSWE {
     static constexpr bool compensated = true;   // two-sum moments dQ = hi + lo
     static constexpr bool tracker(int) { return false; }
 
-    // d(a b / h) = ((a0 db + b0 da + da db) - dh a0 b0 / h0) / h, with the
-    // reference ratio q0 = a0 b0 / h0 formed on the host
-    template <class S, class R>
-    __host__ __device__ static S dprod(R a0, R b0, R q0, const S &da, const S &db, const S &h, const S &dh)
-    {
-        return ((a0 * db + b0 * da + da * db) - dh * q0) / h;
-    }
-
     template <class S, class R>
     __host__ __device__ static void flux_delta(const Phys<R> &p, const S *dQ, S dPhi[][D])
     {
@@ -58,13 +61,13 @@ struct SysSWE {
         const S dh = dQ[0], dmx = dQ[1], dmy = dQ[2];
         const S h = dh + h0;
         const S pres = p.g * dh * (dh * R(0.5) + h0);          // g (h^2 - h0^2) / 2
-        const S xy = dprod(mx0, my0, p.mm0_h0[1], dmx, dmy, h, dh);
+        const S xy = dquot(mx0, my0, p.mm0_h0[1], dmx, dmy, h, dh);
         dPhi[0][0] = dmx;
         dPhi[0][1] = dmy;
-        dPhi[1][0] = pres + dprod(mx0, mx0, p.mm0_h0[0], dmx, dmx, h, dh);
+        dPhi[1][0] = pres + dquot(mx0, mx0, p.mm0_h0[0], dmx, dmx, h, dh);
         dPhi[1][1] = xy;
         dPhi[2][0] = xy;
-        dPhi[2][1] = pres + dprod(my0, my0, p.mm0_h0[2], dmy, dmy, h, dh);
+        dPhi[2][1] = pres + dquot(my0, my0, p.mm0_h0[2], dmy, dmy, h, dh);
     }
 
     template <class S, class R>
@@ -83,6 +86,88 @@ struct SysSWE {
     {
         const R h = Q[0], ux = Q[1] / h, uy = Q[2] / h;
         return sqrt(ux * ux + uy * uy) + sqrt(p.g * h);
+    }
+};
+
+// -------------------------------------------------------------- BURGERS --
+// Inviscid Burgers (Sec. 3): Q = (u), Phi = (u^2 / 2, u^2 / 2), no source.
+// d(u^2 / 2) = du (u0 + du / 2).
+struct SysBurgers {
+    static constexpr int K = 1, D = 2, id = 4;
+    static constexpr bool precise = true;    // float-float equilibrium in single precision
+    static constexpr bool compensated = true;   // two-sum moments dQ = hi + lo
+    static constexpr bool tracker(int) { return false; }
+
+    template <class S, class R>
+    __host__ __device__ static void flux_delta(const Phys<R> &p, const S *dQ, S dPhi[][D])
+    {
+        const S du = dQ[0];
+        const S d = du * (du * R(0.5) + p.Q0[0]);
+        dPhi[0][0] = d;
+        dPhi[0][1] = d;
+    }
+
+    template <class S, class R>
+    __host__ __device__ static void source(const Phys<R> &, const S *, const R *, S *Sk)
+    {
+        Sk[0] = S(R(0));
+    }
+
+    // largest |eigenvalue| of sum_a n_a A_a over unit n: |u| |n0 + n1| <= sqrt(2) |u|
+    template <class R>
+    __host__ __device__ static R max_speed(const Phys<R> &, const R *Q)
+    {
+        return sqrt(R(2)) * fabs(Q[0]);
+    }
+};
+
+// ---------------------------------------------------------------- EULER --
+// Compressible Euler (Sec. 3): Q = (rho, m = rho u, E), ideal gas
+// p = (gamma - 1)(E - |m|^2 / (2 rho)), Phi_rho = m, Phi_m = m (x) m / rho + p I,
+// Phi_E = (E + p) m / rho, no source.  Fluctuation form: every quotient
+// through dquot, dp = (gamma - 1)(dE - (d(mx mx/rho) + d(my my/rho)) / 2)
+// and d(H m_c / rho) with H = E + p.
+struct SysEuler {
+    static constexpr int K = 4, D = 2, id = 5;
+    static constexpr bool precise = true;    // float-float equilibrium in single precision
+    static constexpr bool compensated = true;   // two-sum moments dQ = hi + lo
+    static constexpr bool tracker(int) { return false; }
+
+    template <class S, class R>
+    __host__ __device__ static void flux_delta(const Phys<R> &p, const S *dQ, S dPhi[][D])
+    {
+        const R mx0 = p.Q0[1], my0 = p.Q0[2], H0 = p.H_ref;
+        const S dr = dQ[0], dmx = dQ[1], dmy = dQ[2], dE = dQ[3];
+        const S r = dr + p.Q0[0];
+        const S xx = dquot(mx0, mx0, p.mm0_h0[0], dmx, dmx, r, dr);
+        const S xy = dquot(mx0, my0, p.mm0_h0[1], dmx, dmy, r, dr);
+        const S yy = dquot(my0, my0, p.mm0_h0[2], dmy, dmy, r, dr);
+        const S dp = (p.gamma - R(1)) * (dE - (xx + yy) * R(0.5));
+        const S dH = dE + dp;
+        dPhi[0][0] = dmx;
+        dPhi[0][1] = dmy;
+        dPhi[1][0] = xx + dp;
+        dPhi[1][1] = xy;
+        dPhi[2][0] = xy;
+        dPhi[2][1] = yy + dp;
+        dPhi[3][0] = dquot(H0, mx0, p.Hu_ref[0], dH, dmx, r, dr);
+        dPhi[3][1] = dquot(H0, my0, p.Hu_ref[1], dH, dmy, r, dr);
+    }
+
+    template <class S, class R>
+    __host__ __device__ static void source(const Phys<R> &, const S *, const R *, S *Sk)
+    {
+#pragma unroll
+        for (int k = 0; k < K; ++k) Sk[k] = S(R(0));
+    }
+
+    // |u| + c, c = sqrt(gamma p / rho)
+    template <class R>
+    __host__ __device__ static R max_speed(const Phys<R> &p, const R *Q)
+    {
+        const R r = Q[0], ux = Q[1] / r, uy = Q[2] / r;
+        const R pr = (p.gamma - R(1)) * (Q[3] - R(0.5) * r * (ux * ux + uy * uy));
+        return sqrt(ux * ux + uy * uy) + sqrt(p.gamma * (pr > R(0) ? pr : R(0)) / r);
     }
 };
 

@@ -131,6 +131,12 @@ PRESETS = {
     "neohooke2048": Preset("neohooke2048", "neohooke2d", "D2Q9", 2048, "f16", 2000,
                            "acoustic", 0.1, 2.0, None,
                            {"rho0": 1.0, "mu_s": 1.0, "lambda_s": 2.0}),
+    # the paper's suite on the same kernel (single-precision recipes of its
+    # configuration table, D2Q5 as in the paper)
+    "burgers2048": Preset("burgers2048", "burgers2d", "D2Q5", 2048, "f32", 100,
+                          "acoustic", 0.2, 2.0, None, {}),
+    "euler2048": Preset("euler2048", "euler2d", "D2Q5", 2048, "f32", 100,
+                        "acoustic", 0.05, 5.0, None, {"gamma": 1.4}),
 }
 
 # Seeds of the random fields.
@@ -185,6 +191,25 @@ def topography_gradient(n: int, seed: int = SEED_TOPOGRAPHY):
     m = draw_modes(seed, 8, 4, 0.01 / 8.0)
     _, gx, gy = fourier_field(n, m)
     return np.stack([gx, gy])
+
+
+def burgers_initial(n: int, amp: float = 1.3):
+    """The paper's Burgers profile at t = 0: u = A sin(2 pi x) sin(2 pi y), [1, n, n]."""
+    X, Y = grid2(n)
+    k = 2.0 * math.pi
+    return (amp * np.sin(k * X) * np.sin(k * Y))[None]
+
+
+def euler_initial(n: int, gamma: float = 1.4):
+    """The paper's Euler profile at t = 0 in units rho0 = cs = 1: rho = 1 +
+    0.3 sin(2 pi x) cos(2 pi y), velocity (3, 3) (the velocity and pressure
+    modes carry sin t), p = 1/gamma + (rho - 1); conserved [4, n, n]."""
+    X, Y = grid2(n)
+    k = 2.0 * math.pi
+    rho = 1.0 + 0.3 * np.sin(k * X) * np.cos(k * Y)
+    p = 1.0 / gamma + (rho - 1.0)
+    E = p / (gamma - 1.0) + 0.5 * rho * (3.0 ** 2 + 3.0 ** 2)
+    return np.stack([rho, 3.0 * rho, 3.0 * rho, E])
 
 
 def neohooke_initial(n: int, seeds=SEED_DISPLACEMENT):
