@@ -32,11 +32,12 @@
 #define MAXK 17
 #define MAXQ 9
 
-enum { SYS_ADVDIFF = 0, SYS_SWE = 1, SYS_NEOHOOKE = 2, SYS_NSF17 = 3, SYS_BURGERS = 4, SYS_EULER = 5 };
+enum { SYS_ADVDIFF = 0, SYS_SWE = 1, SYS_NEOHOOKE = 2, SYS_NSF17 = 3, SYS_BURGERS = 4, SYS_EULER = 5,
+       SYS_MAXWELL = 6, SYS_ALLENCAHN = 7 };
 enum { LAT_D2Q5 = 0, LAT_D2Q9 = 1, LAT_D3Q7 = 2 };
 enum {
     P_G = 0, P_AX, P_AY, P_AZ, P_NU, P_R, P_TAUG, P_GAMMA, P_MU, P_KAPPA,
-    P_RHO0, P_MUS, P_LAMS, P_COUNT
+    P_RHO0, P_MUS, P_LAMS, P_CLIGHT, P_COUNT
 };
 
 typedef struct {
@@ -100,6 +101,8 @@ static int system_K(int sys)
     case SYS_NSF17: return 17;
     case SYS_BURGERS: return 1;
     case SYS_EULER: return 4;
+    case SYS_MAXWELL: return 3;
+    case SYS_ALLENCAHN: return 3;
     }
     return 0;
 }

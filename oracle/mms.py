@@ -20,6 +20,8 @@ Cases:
 * ``burgers_paper`` -- the paper's inviscid-Burgers MMS (amplitude 1.3).
 * ``euler_paper`` -- the paper's compressible-Euler MMS, nondimensional
   (rho0 = 1, cs = 1: background Mach 3 per axis).
+* ``maxwell_paper`` -- the paper's Maxwell TM MMS (c = 1).
+* ``allencahn_paper`` -- the paper's Allen-Cahn MMS, trackers exact.
 * ``nsf17``      -- the 3D compressible NSF manufactured solution with the
   shapes of the paper's homogenized-NSF MMS (porosity 1), conserved rows
   forced; tracker rows are forced only when ``force_trackers`` is set.
@@ -129,6 +131,38 @@ def euler_paper(rho0=1.0, cs=1.0, gamma=1.4):
     res = [sp.diff(Q[k], T) + _div(Phi[k], (X, Y)) for k in range(4)]
     fQ = sp.lambdify((X, Y, T), Q, "numpy")
     fS = sp.lambdify((X, Y, T), res, "numpy", cse=True)
+    return _wrap2(fQ), _wrap2(fS)
+
+
+# ------------------------------------------------------------ MAXWELL ----
+@functools.lru_cache(maxsize=None)
+def maxwell_paper(amp=0.5, omega=4.0, c=1.0):
+    """The paper's Maxwell TM MMS (supplement, Maxwell MMS): kx = 2 pi,
+    ky = 4 pi, E_z ~ cos(omega t), H ~ sin(omega t), div H = 0."""
+    A, w, cc = sp.Float(amp), sp.Float(omega), sp.Float(c)
+    kx, ky = PI2, 2 * PI2
+    Ez = A * sp.sin(kx * X) * sp.sin(ky * Y) * sp.cos(w * T)
+    Hx = A * sp.sin(kx * X) * sp.cos(ky * Y) * sp.sin(w * T)
+    Hy = -A * (kx / ky) * sp.cos(kx * X) * sp.sin(ky * Y) * sp.sin(w * T)
+    Q = [Ez, Hx, Hy]
+    Phi = [[-cc * Hy, cc * Hx], [sp.Integer(0), cc * Ez], [-cc * Ez, sp.Integer(0)]]
+    res = [sp.diff(Q[k], T) + _div(Phi[k], (X, Y)) for k in range(3)]
+    fQ = sp.lambdify((X, Y, T), Q, "numpy")
+    fS = sp.lambdify((X, Y, T), res, "numpy", cse=True)
+    return _wrap2(fQ), _wrap2(fS)
+
+
+# --------------------------------------------------------- ALLEN-CAHN ----
+@functools.lru_cache(maxsize=None)
+def allencahn_paper(gamma=0.01, r=1.0):
+    """The paper's Allen-Cahn MMS (supplement, Allen-Cahn MMS):
+    phi = 0.7 sin(2 pi x) cos(2 pi y) cos t, trackers exact (grad phi), not
+    forced; the phi row is forced with the flux at the exact trackers."""
+    phi = sp.Rational(7, 10) * sp.sin(PI2 * X) * sp.cos(PI2 * Y) * sp.cos(T)
+    gx, gy = sp.diff(phi, X), sp.diff(phi, Y)
+    res = sp.diff(phi, T) + _div([-gamma * gx, -gamma * gy], (X, Y)) - r * (phi - phi ** 3)
+    fQ = sp.lambdify((X, Y, T), [phi, gx, gy], "numpy")
+    fS = sp.lambdify((X, Y, T), [res, sp.Integer(0), sp.Integer(0)], "numpy", cse=True)
     return _wrap2(fQ), _wrap2(fS)
 
 
