@@ -187,6 +187,10 @@ def extra_runs(torch, lbm, inputs):
     one("burgers2d_D2Q5_f32_2048", p, 2048, "f32", 200, 40, inputs.burgers_initial(2048))
     p = inputs.PRESETS["euler2048"]
     one("euler2d_D2Q5_f32_2048", p, 2048, "f32", 200, 160, inputs.euler_initial(2048))
+    p = inputs.PRESETS["maxwell2048"]
+    one("maxwell2d_D2Q5_f32_2048", p, 2048, "f32", 200, 120, inputs.maxwell_initial(2048))
+    p = inputs.PRESETS["allencahn2048"]
+    one("allencahn_trk2d_D2Q5_f32_2048", p, 2048, "f32", 200, 120, inputs.allencahn_initial(2048))
     p = inputs.PRESETS["advdiff64"]
     one("advdiff_D2Q5_f64_64", p, 64, "f64", 200, 240, inputs.advdiff_initial(64))
     p = inputs.PRESETS["nsf256"]

@@ -8,7 +8,10 @@
 
 #include "systems.hpp"
 
-enum { SYS_ADVDIFF = 0, SYS_SWE = 1, SYS_NEOHOOKE = 2, SYS_NSF17 = 3, SYS_BURGERS = 4, SYS_EULER = 5 };
+enum {
+    SYS_ADVDIFF = 0, SYS_SWE = 1, SYS_NEOHOOKE = 2, SYS_NSF17 = 3, SYS_BURGERS = 4, SYS_EULER = 5,
+    SYS_MAXWELL = 6, SYS_ALLENCAHN = 7
+};
 enum { LAT_D2Q5 = 0, LAT_D2Q9 = 1, LAT_D3Q7 = 2 };
 
 #ifndef LBM_BLOCK
@@ -89,6 +92,7 @@ struct lbm_state_impl {
     double g = 1.0, ax = 0, ay = 0, nu = 0, react = 0, g_tau = -1;
     double gamma = 1.4, mu = 0, kappa = 0;
     double rho0_el = 1.0, mu_s = 1.0, lam_s = 1.0;
+    double c_light = 1.0;
     int mms_on = 0;
     double mms_amp = 0.05, mms_rho0 = 1.0, mms_p0 = 1.0, mms_u0 = 0.0;
     double t0 = 0.0;

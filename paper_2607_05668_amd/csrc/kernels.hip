@@ -718,6 +718,7 @@ KParams<R> lbm_state_impl::kparams(double t_half) const
         bool trk = false;
         if (sys == SYS_ADVDIFF) trk = SysAdvDiff::tracker(k);
         if (sys == SYS_NSF17) trk = SysNSF17::tracker(k);
+        if (sys == SYS_ALLENCAHN) trk = SysAllenCahn::tracker(k);
         const double om = trk ? omega_t : omega_c;
         p.omega[k] = (R)om;
         p.delta[k] = (R)(2.0 - om);
@@ -730,6 +731,7 @@ KParams<R> lbm_state_impl::kparams(double t_half) const
     std::memset(&d, 0, sizeof d);
     for (int k = 0; k < LBM_MAXK; ++k) d.Q0[k] = Q0[k];
     d.g = g;
+    d.c_light = c_light;
     d.a[0] = ax;
     d.a[1] = ay;
     d.nu = nu;
@@ -778,6 +780,7 @@ KParams<R> lbm_state_impl::kparams(double t_half) const
     // convert
     for (int k = 0; k < LBM_MAXK; ++k) p.phys.Q0[k] = (R)d.Q0[k];
     p.phys.g = (R)d.g;
+    p.phys.c_light = (R)d.c_light;
     for (int j = 0; j < 3; ++j) {
         p.phys.mm0_h0[j] = (R)d.mm0_h0[j];
         p.phys.Hu_ref[j] = (R)d.Hu_ref[j];
@@ -968,6 +971,14 @@ const Launchers *lbm_launchers(int sys, int lat, int storage)
     case SYS_EULER:
         if (lat == LAT_D2Q5) return by_storage<SysEuler, D2Q5>(storage);
         if (lat == LAT_D2Q9) return by_storage<SysEuler, D2Q9>(storage);
+        break;
+    case SYS_MAXWELL:
+        if (lat == LAT_D2Q5) return by_storage<SysMaxwell, D2Q5>(storage);
+        if (lat == LAT_D2Q9) return by_storage<SysMaxwell, D2Q9>(storage);
+        break;
+    case SYS_ALLENCAHN:
+        if (lat == LAT_D2Q5) return by_storage<SysAllenCahn, D2Q5>(storage);
+        if (lat == LAT_D2Q9) return by_storage<SysAllenCahn, D2Q9>(storage);
         break;
     }
     return nullptr;

@@ -451,6 +451,14 @@ const Launchers *lbm_launchers_ne(int sys, int lat)
         if (lat == LAT_D2Q5) return ImplNE<SysEuler, D2Q5>::get();
         if (lat == LAT_D2Q9) return ImplNE<SysEuler, D2Q9>::get();
         break;
+    case SYS_MAXWELL:
+        if (lat == LAT_D2Q5) return ImplNE<SysMaxwell, D2Q5>::get();
+        if (lat == LAT_D2Q9) return ImplNE<SysMaxwell, D2Q9>::get();
+        break;
+    case SYS_ALLENCAHN:
+        if (lat == LAT_D2Q5) return ImplNE<SysAllenCahn, D2Q5>::get();
+        if (lat == LAT_D2Q9) return ImplNE<SysAllenCahn, D2Q9>::get();
+        break;
     }
     return nullptr;
 }

@@ -39,6 +39,8 @@ int system_id(const char *s)
     if (!std::strcmp(s, "nsf3d_trk17")) return SYS_NSF17;
     if (!std::strcmp(s, "burgers2d")) return SYS_BURGERS;
     if (!std::strcmp(s, "euler2d")) return SYS_EULER;
+    if (!std::strcmp(s, "maxwell2d")) return SYS_MAXWELL;
+    if (!std::strcmp(s, "allencahn_trk2d")) return SYS_ALLENCAHN;
     return -1;
 }
 
@@ -51,8 +53,8 @@ int lattice_id(const char *s)
     return -1;
 }
 
-const int kSysK[6] = {3, 3, 6, 17, 1, 4};
-const int kSysD[6] = {2, 2, 2, 3, 2, 2};
+const int kSysK[8] = {3, 3, 6, 17, 1, 4, 3, 3};
+const int kSysD[8] = {2, 2, 2, 3, 2, 2, 2, 2};
 const int kLatQ[3] = {5, 9, 7};
 const int kLatD[3] = {2, 2, 3};
 const double kLatCs2[3] = {1.0 / 3.0, 1.0 / 3.0, 1.0 / 4.0};
@@ -92,7 +94,7 @@ void default_reference(lbm_state *h)
     }
 }
 
-bool has_trackers(int sys) { return sys == SYS_ADVDIFF || sys == SYS_NSF17; }
+bool has_trackers(int sys) { return sys == SYS_ADVDIFF || sys == SYS_NSF17 || sys == SYS_ALLENCAHN; }
 
 size_t arith_bytes(const lbm_state *h) { return h->storage == LBM_F64 ? 8 : 4; }
 
@@ -208,6 +210,22 @@ int lbm_set_param(lbm_state *h, const char *name, double v)
         if (n == "lambda_s") { h->lam_s = v; return LBM_OK; }
         break;
     case SYS_BURGERS:
+        break;
+    case SYS_MAXWELL:
+        if (n == "c") {
+            if (!(v > 0)) return fail(h, LBM_EINVAL, "c must be positive");
+            h->c_light = v;
+            return LBM_OK;
+        }
+        break;
+    case SYS_ALLENCAHN:
+        if (n == "nu") { h->nu = v; return LBM_OK; }
+        if (n == "R") { h->react = v; return LBM_OK; }
+        if (n == "g_tau") {
+            if (!(v > 0)) return fail(h, LBM_EINVAL, "g_tau must be positive");
+            h->g_tau = v;
+            return LBM_OK;
+        }
         break;
     case SYS_EULER:
         if (n == "gamma") {

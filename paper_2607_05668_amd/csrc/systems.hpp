@@ -31,6 +31,7 @@ struct Phys {
     R p_ref, T_ref, H_ref;// reference pressure, temperature p0/rho0, E0 + p0
     R tau_ref[9];         // viscous stress of the reference trackers
     R rho0, mu_s, lam_s;  // elasticity
+    R c_light;            // Maxwell wave speed
     R H0[4];              // F0 - I (reference deformation minus identity)
     R P0[4];              // first Piola-Kirchhoff stress at F0
 };
@@ -168,6 +169,82 @@ struct SysEuler {
         const R r = Q[0], ux = Q[1] / r, uy = Q[2] / r;
         const R pr = (p.gamma - R(1)) * (Q[3] - R(0.5) * r * (ux * ux + uy * uy));
         return sqrt(ux * ux + uy * uy) + sqrt(p.gamma * (pr > R(0) ? pr : R(0)) / r);
+    }
+};
+
+// -------------------------------------------------------------- MAXWELL --
+// Maxwell, transverse-magnetic mode in vacuum (Sec. 3): Q = (E_z, H_x, H_y),
+// Phi_Ez = c (-H_y, H_x), Phi_Hx = c (0, E_z), Phi_Hy = c (-E_z, 0), no
+// source.  Linear, so dPhi is the flux of dQ.
+struct SysMaxwell {
+    static constexpr int K = 3, D = 2, id = 6;
+    static constexpr bool precise = true;    // float-float equilibrium in single precision
+    static constexpr bool compensated = true;   // two-sum moments dQ = hi + lo
+    static constexpr bool tracker(int) { return false; }
+
+    template <class S, class R>
+    __host__ __device__ static void flux_delta(const Phys<R> &p, const S *dQ, S dPhi[][D])
+    {
+        const R c = p.c_light;
+        dPhi[0][0] = dQ[2] * (-c);
+        dPhi[0][1] = dQ[1] * c;
+        dPhi[1][0] = S(R(0));
+        dPhi[1][1] = dQ[0] * c;
+        dPhi[2][0] = dQ[0] * (-c);
+        dPhi[2][1] = S(R(0));
+    }
+
+    template <class S, class R>
+    __host__ __device__ static void source(const Phys<R> &, const S *, const R *, S *Sk)
+    {
+#pragma unroll
+        for (int k = 0; k < K; ++k) Sk[k] = S(R(0));
+    }
+
+    // flux Jacobian eigenvalues {+c, -c, 0} in every direction
+    template <class R>
+    __host__ __device__ static R max_speed(const Phys<R> &p, const R *)
+    {
+        return fabs(p.c_light);
+    }
+};
+
+// ----------------------------------------------------------- ALLEN-CAHN --
+// Allen-Cahn phase field with one gradient tracker (Sec. 3):
+// Q = (phi, G), Phi_phi = -gamma G, Phi_G = -I phi / tau_grad,
+// S_phi = r (phi - phi^3), S_G = -G / tau_grad; gamma in nu, r in react.
+struct SysAllenCahn {
+    static constexpr int K = 3, D = 2, id = 7;
+    static constexpr bool precise = true;    // float-float equilibrium in single precision
+    static constexpr bool compensated = true;   // two-sum moments dQ = hi + lo
+    static constexpr bool tracker(int k) { return k > 0; }
+
+    template <class S, class R>
+    __host__ __device__ static void flux_delta(const Phys<R> &p, const S *dQ, S dPhi[][D])
+    {
+        const S dpi = dQ[0] * (-p.inv_tau_grad);
+        dPhi[0][0] = dQ[1] * (-p.nu);
+        dPhi[0][1] = dQ[2] * (-p.nu);
+        dPhi[1][0] = dpi;
+        dPhi[1][1] = S(R(0));
+        dPhi[2][0] = S(R(0));
+        dPhi[2][1] = dpi;
+    }
+
+    template <class S, class R>
+    __host__ __device__ static void source(const Phys<R> &p, const S *dQ, const R *, S *Sk)
+    {
+        const S phi = dQ[0] + p.Q0[0];
+        Sk[0] = (phi - phi * phi * phi) * p.react;
+        Sk[1] = (dQ[1] + p.Q0[1]) * (-p.inv_tau_grad);
+        Sk[2] = (dQ[2] + p.Q0[2]) * (-p.inv_tau_grad);
+    }
+
+    // eigenvalues of the (phi, G_n) block: +- sqrt(gamma / tau_grad)
+    template <class R>
+    __host__ __device__ static R max_speed(const Phys<R> &p, const R *)
+    {
+        return sqrt(p.nu * p.inv_tau_grad);
     }
 };
 

@@ -137,6 +137,10 @@ PRESETS = {
                           "acoustic", 0.2, 2.0, None, {}),
     "euler2048": Preset("euler2048", "euler2d", "D2Q5", 2048, "f32", 100,
                         "acoustic", 0.05, 5.0, None, {"gamma": 1.4}),
+    "maxwell2048": Preset("maxwell2048", "maxwell2d", "D2Q5", 2048, "f32", 100,
+                          "acoustic", 0.2, 0.2, None, {"c": 1.0}),
+    "allencahn2048": Preset("allencahn2048", "allencahn_trk2d", "D2Q5", 2048, "f32", 100,
+                            "diffusive", 1.9, 50.0, 6.0, {"nu": 0.01, "R": 1.0}),
 }
 
 # Seeds of the random fields.
@@ -210,6 +214,22 @@ def euler_initial(n: int, gamma: float = 1.4):
     p = 1.0 / gamma + (rho - 1.0)
     E = p / (gamma - 1.0) + 0.5 * rho * (3.0 ** 2 + 3.0 ** 2)
     return np.stack([rho, 3.0 * rho, 3.0 * rho, E])
+
+
+def maxwell_initial(n: int, amp: float = 0.5):
+    """The paper's TM pattern at t = 0: E_z = A sin(2 pi x) sin(4 pi y), H = 0."""
+    X, Y = grid2(n)
+    Ez = amp * np.sin(2.0 * math.pi * X) * np.sin(4.0 * math.pi * Y)
+    return np.stack([Ez, np.zeros_like(Ez), np.zeros_like(Ez)])
+
+
+def allencahn_initial(n: int, amp: float = 0.7):
+    """The paper's Allen-Cahn profile at t = 0, phi = 0.7 sin(2 pi x) cos(2 pi y),
+    with its analytic gradient as the tracker fields, [3, n, n]."""
+    X, Y = grid2(n)
+    k = 2.0 * math.pi
+    phi = amp * np.sin(k * X) * np.cos(k * Y)
+    return np.stack([phi, amp * k * np.cos(k * X) * np.cos(k * Y), -amp * k * np.sin(k * X) * np.sin(k * Y)])
 
 
 def neohooke_initial(n: int, seeds=SEED_DISPLACEMENT):

@@ -31,10 +31,10 @@ def grid(nx, ny):
     return X, Y
 
 
-def run_pair(system, lattice, shape, f, tau_r, steps, storage, params, fQ):
+def run_pair(system, lattice, shape, f, tau_r, steps, storage, params, fQ, diffusive=False):
     ny, nx = shape
     dx = 1.0 / max(nx, ny)
-    dt = f * dx
+    dt = f * dx * dx if diffusive else f * dx
     tau = 0.5 + tau_r * dt
     X, Y = grid(nx, ny)
     Q = fQ(X, Y, 0.0)
@@ -42,8 +42,12 @@ def run_pair(system, lattice, shape, f, tau_r, steps, storage, params, fQ):
     g.init(Q)
     g.step(steps)
     Qg = g.moments().cpu().numpy()
-    o = oracle.Oracle(system, lattice, shape, g.param("dt"), g.param("dx"), 1.0 / g.param("omega"), None, params,
-                      Q0=g.reference)
+    phys = {k: v for k, v in params.items() if k != "g_tau"}
+    trk = {}
+    if "g_tau" in params:
+        trk = {"omega_tracker": g.param("omega_tracker")}
+    o = oracle.Oracle(system, lattice, shape, g.param("dt"), g.param("dx"), 1.0 / g.param("omega"),
+                      g.param("g_tau") if "g_tau" in params else None, phys, Q0=g.reference, **trk)
     o.init(Q)
     o.step(steps)
     return Qg, o.moments()
@@ -98,3 +102,33 @@ def test_euler_conserves_mass_momentum_energy():
     g.step(500)
     s1 = g.reduce(lbm.RED_SUMS)
     assert np.allclose(s1, s0, rtol=1e-12, atol=1e-9)
+
+
+@pytest.mark.parametrize("lattice,shape,storage,tol", [
+    ("D2Q5", (128, 128), "f32", 1e-6), ("D2Q9", (50, 70), "f32", 1e-6),
+    ("D2Q5", (64, 64), "f64", 1e-12), ("D2Q9", (128, 128), "f16ne", 1e-3)])
+def test_maxwell_matches_oracle(lattice, shape, storage, tol):
+    """The paper's TM pattern at t = 0 (E_z only), a free linear wave at c = 1
+    with the recipe f = 0.2, tau_R = 0.2."""
+    print(f"maxwell2d {lattice} {storage} {shape} 300 steps", flush=True)
+    fQ, _ = mms.maxwell_paper()
+    Qg, Qo = run_pair("maxwell2d", lattice, shape, 0.2, 0.2, 300, storage, {"c": 1.0}, fQ)
+    errs = {"Ez": rel(Qg[0], Qo[0]), "H": rel(Qg[1:], Qo[1:])}
+    print("rel L2", {k: f"{v:.3e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= tol, k
+
+
+@pytest.mark.parametrize("lattice,shape,storage,tol", [
+    ("D2Q5", (64, 64), "f32", 1e-6), ("D2Q9", (40, 56), "f32", 1e-6), ("D2Q5", (64, 64), "f64", 1e-12)])
+def test_allencahn_matches_oracle(lattice, shape, storage, tol):
+    """The paper's Allen-Cahn profile at t = 0 with exact trackers, diffusive
+    recipe f = 1.9, tau_R = 50, g_tau = 6 (gamma = 0.01, r = 1)."""
+    print(f"allencahn_trk2d {lattice} {storage} {shape} 500 steps", flush=True)
+    fQ, _ = mms.allencahn_paper()
+    Qg, Qo = run_pair("allencahn_trk2d", lattice, shape, 1.9, 50.0, 500, storage,
+                      {"nu": 0.01, "R": 1.0, "g_tau": 6.0}, fQ, diffusive=True)
+    errs = {"phi": rel(Qg[0], Qo[0]), "G": rel(Qg[1:], Qo[1:])}
+    print("rel L2", {k: f"{v:.3e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= tol, k
