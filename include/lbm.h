@@ -77,6 +77,11 @@ enum {                      /* lbm_reduce: what                                 
  *            "nsf3d_trk17"   3D compressible NSF with 9 velocity-gradient and
  *                            3 temperature-gradient trackers (Sec. 3, the
  *                            homogenized NSF case at porosity 1, full tracker basis)
+ *            "burgers2d"     inviscid Burgers (u), Sec. 3
+ *            "euler2d"       compressible Euler (rho, rho u0, rho u1, E), ideal gas, Sec. 3
+ *            "maxwell2d"     Maxwell, transverse-magnetic mode (E_z, H_x, H_y), Sec. 3
+ *            "allencahn_trk2d" Allen-Cahn phase field with a gradient
+ *                            tracker (phi, G_phi), Sec. 3
  *   lattice: "D2Q5" | "D2Q9" (2D systems) | "D3Q7" (3D systems)
  *   nx, ny, nz: grid; nz must be 1 in 2D (rows whose length is a multiple
  *   of 64 map onto whole wavefronts; any size is accepted).
@@ -100,6 +105,10 @@ int lbm_num_velocities(const lbm_state *h);
  *   neohooke2d:     rho0, mu_s, lambda_s
  *   nsf3d_trk17:    gamma, mu, kappa, g_tau, mms (0/1: built-in manufactured-
  *                   solution forcing), mms_amp, mms_rho0, mms_p0, mms_u0
+ *   burgers2d:      (none)
+ *   euler2d:        gamma (adiabatic index, default 1.4)
+ *   maxwell2d:      c (wave speed, default 1)
+ *   allencahn_trk2d: nu (interface diffusivity gamma), R (reaction rate r), g_tau
  *   all:            t0 (initial time) */
 int lbm_set_param(lbm_state *h, const char *name, double v);
 
@@ -121,7 +130,9 @@ int lbm_set_storage(lbm_state *h, int storage);
  * For F32/F16 storage it is rounded to the nearest float; lbm_get_reference
  * returns the value in use.  Defaults: swe2d (1,0,0); advdiff (1,0,0);
  * neohooke2d (1,0,0,1,0,0); nsf3d_trk17 (1, u0,u0,u0, E0, 0...) from the
- * mms_* parameters. */
+ * mms_* parameters; euler2d (1, 3, 3, 1/(gamma (gamma-1)) + 9), the
+ * Mach-3 background of the paper's manufactured solution in units
+ * rho0 = cs = 1; burgers2d, maxwell2d, allencahn_trk2d all zeros. */
 int lbm_set_reference(lbm_state *h, const double *Q0);
 int lbm_get_reference(const lbm_state *h, double *Q0_out);
 
