@@ -33,11 +33,11 @@
 #define MAXQ 9
 
 enum { SYS_ADVDIFF = 0, SYS_SWE = 1, SYS_NEOHOOKE = 2, SYS_NSF17 = 3, SYS_BURGERS = 4, SYS_EULER = 5,
-       SYS_MAXWELL = 6, SYS_ALLENCAHN = 7 };
+       SYS_MAXWELL = 6, SYS_ALLENCAHN = 7, SYS_RELHYDRO = 8, SYS_NSE = 9 };
 enum { LAT_D2Q5 = 0, LAT_D2Q9 = 1, LAT_D3Q7 = 2 };
 enum {
     P_G = 0, P_AX, P_AY, P_AZ, P_NU, P_R, P_TAUG, P_GAMMA, P_MU, P_KAPPA,
-    P_RHO0, P_MUS, P_LAMS, P_CLIGHT, P_COUNT
+    P_RHO0, P_MUS, P_LAMS, P_CLIGHT, P_CSPHYS, P_COUNT
 };
 
 typedef struct {
@@ -103,6 +103,8 @@ static int system_K(int sys)
     case SYS_EULER: return 4;
     case SYS_MAXWELL: return 3;
     case SYS_ALLENCAHN: return 3;
+    case SYS_RELHYDRO: return 3;
+    case SYS_NSE: return 7;
     }
     return 0;
 }
@@ -111,18 +113,22 @@ static int system_K(int sys)
 #define T double
 #define FN(name) name##_re
 #define LOG(x) log(x)
+#define SQRT(x) sqrt(x)
 #include "oracle_cell.inc"
 #undef T
 #undef FN
 #undef LOG
+#undef SQRT
 
 #define T double complex
 #define FN(name) name##_cx
 #define LOG(x) clog(x)
+#define SQRT(x) csqrt(x)
 #include "oracle_cell.inc"
 #undef T
 #undef FN
 #undef LOG
+#undef SQRT
 
 static void reference_flux(const oracle_cfg *cfg, int K, double *F0)
 {

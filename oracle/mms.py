@@ -22,6 +22,9 @@ Cases:
   (rho0 = 1, cs = 1: background Mach 3 per axis).
 * ``maxwell_paper`` -- the paper's Maxwell TM MMS (c = 1).
 * ``allencahn_paper`` -- the paper's Allen-Cahn MMS, trackers exact.
+* ``relhydro_paper`` -- the paper's ultrarelativistic-fluid MMS.
+* ``nse_paper``  -- the paper's weakly compressible NSE (Taylor-Green) MMS,
+  nondimensional, trackers exact.
 * ``nsf17``      -- the 3D compressible NSF manufactured solution with the
   shapes of the paper's homogenized-NSF MMS (porosity 1), conserved rows
   forced; tracker rows are forced only when ``force_trackers`` is set.
@@ -163,6 +166,67 @@ def allencahn_paper(gamma=0.01, r=1.0):
     res = sp.diff(phi, T) + _div([-gamma * gx, -gamma * gy], (X, Y)) - r * (phi - phi ** 3)
     fQ = sp.lambdify((X, Y, T), [phi, gx, gy], "numpy")
     fS = sp.lambdify((X, Y, T), [res, sp.Integer(0), sp.Integer(0)], "numpy", cse=True)
+    return _wrap2(fQ), _wrap2(fS)
+
+
+# -------------------------------------------------- ULTRARELATIVISTIC ----
+def relhydro_exact_exprs():
+    """The paper's ultrarelativistic MMS (supplement): fluctuations of 0.4 about
+    (E, S0, S1) = (3, 1.2, 1.2)."""
+    a = sp.Rational(2, 5)
+    E = a * sp.sin(PI2 * X) * sp.sin(PI2 * Y) * sp.cos(T) + 3
+    S0 = a * sp.cos(PI2 * X) * sp.cos(PI2 * Y) * sp.sin(T) + sp.Rational(6, 5)
+    S1 = a * sp.sin(PI2 * X) * sp.sin(PI2 * Y) * sp.sin(T) + sp.Rational(6, 5)
+    return [E, S0, S1]
+
+
+@functools.lru_cache(maxsize=None)
+def relhydro_paper():
+    Q = relhydro_exact_exprs()
+    E, S0, S1 = Q
+    p = (sp.sqrt(4 * E ** 2 - 3 * (S0 ** 2 + S1 ** 2)) - E) / 3
+    v = [S0 / (E + p), S1 / (E + p)]
+    Phi = [[S0, S1], [S0 * v[0] + p, S0 * v[1]], [S1 * v[0], S1 * v[1] + p]]
+    res = [sp.diff(Q[k], T) + _div(Phi[k], (X, Y)) for k in range(3)]
+    fQ = sp.lambdify((X, Y, T), Q, "numpy")
+    fS = sp.lambdify((X, Y, T), res, "numpy", cse=True)
+    return _wrap2(fQ), _wrap2(fS)
+
+
+# ----------------------------------------------------------------- NSE ----
+def nse_exact_exprs(rho0=1.0, cs=1.0, U=0.1, mu=0.01):
+    """The paper's weakly compressible NSE MMS (supplement): Taylor-Green
+    vortex with decay D = exp(-2 (nu / cs) k^2 t), rho = rho0 + p / cs^2,
+    m = rho u; read nondimensionally (rho0 = cs = 1, U = 0.1, mu = 0.01:
+    Ma 0.1, Re 10).  Returns (rho, m0, m1) and the exact trackers d_b m_a."""
+    r0, c, Uu = sp.Float(rho0), sp.Float(cs), sp.Float(U)
+    nu = sp.Float(mu) / r0
+    k = PI2
+    Dc = sp.exp(-2 * (nu / c) * k ** 2 * T)
+    u = -Uu * sp.cos(k * X) * sp.sin(k * Y) * Dc
+    v = Uu * sp.sin(k * X) * sp.cos(k * Y) * Dc
+    p = -sp.Rational(1, 4) * r0 * Uu ** 2 * (sp.cos(2 * k * X) + sp.cos(2 * k * Y)) * Dc ** 2
+    rho = r0 + p / c ** 2
+    m = [rho * u, rho * v]
+    G = [[sp.diff(m[a], (X, Y)[b]) for b in range(2)] for a in range(2)]
+    return [rho, m[0], m[1]], G
+
+
+@functools.lru_cache(maxsize=None)
+def nse_paper(rho0=1.0, cs=1.0, U=0.1, mu=0.01):
+    """Conserved rows forced with the flux at the exact trackers; tracker rows
+    not forced (as for the other tracker systems)."""
+    (rho, m0, m1), G = nse_exact_exprs(rho0, cs, U, mu)
+    m = [m0, m1]
+    cs2, muf = sp.Float(cs) ** 2, sp.Float(mu)
+    Phi = [[m0, m1]]
+    for a in range(2):
+        Phi.append([m[a] * m[c] / rho + (rho * cs2 if a == c else 0) - muf * (G[a][c] + G[c][a]) / rho
+                    for c in range(2)])
+    Q = [rho, m0, m1, G[0][0], G[0][1], G[1][0], G[1][1]]
+    res = [sp.diff(Q[k], T) + _div(Phi[k], (X, Y)) for k in range(3)] + [sp.Integer(0)] * 4
+    fQ = sp.lambdify((X, Y, T), Q, "numpy")
+    fS = sp.lambdify((X, Y, T), res, "numpy", cse=True)
     return _wrap2(fQ), _wrap2(fS)
 
 
