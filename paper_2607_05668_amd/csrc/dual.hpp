@@ -87,3 +87,17 @@ __host__ __device__ inline Dual<R, N> lbm_log1p(const Dual<R, N> &a)
     for (int j = 0; j < N; ++j) r.d[j] = a.d[j] * s;
     return r;
 }
+
+// sqrt(x) and its derivative 1 / (2 sqrt(x))
+__host__ __device__ inline float lbm_sqrt(float x) { return sqrtf(x); }
+__host__ __device__ inline double lbm_sqrt(double x) { return sqrt(x); }
+template <class R, int N>
+__host__ __device__ inline Dual<R, N> lbm_sqrt(const Dual<R, N> &a)
+{
+    Dual<R, N> r;
+    r.v = lbm_sqrt(a.v);
+    const R s = R(0.5) / r.v;
+#pragma unroll
+    for (int j = 0; j < N; ++j) r.d[j] = a.d[j] * s;
+    return r;
+}

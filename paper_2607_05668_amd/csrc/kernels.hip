@@ -719,6 +719,7 @@ KParams<R> lbm_state_impl::kparams(double t_half) const
         if (sys == SYS_ADVDIFF) trk = SysAdvDiff::tracker(k);
         if (sys == SYS_NSF17) trk = SysNSF17::tracker(k);
         if (sys == SYS_ALLENCAHN) trk = SysAllenCahn::tracker(k);
+        if (sys == SYS_NSE) trk = SysNSE::tracker(k);
         const double om = trk ? omega_t : omega_c;
         p.omega[k] = (R)om;
         p.delta[k] = (R)(2.0 - om);
@@ -758,11 +759,20 @@ KParams<R> lbm_state_impl::kparams(double t_half) const
             for (int b = 0; b < 3; ++b)
                 d.tau_ref[3 * a + b] = mu * (Q0[5 + 3 * a + b] + Q0[5 + 3 * b + a] - (a == b ? 2.0 / 3.0 * trG : 0.0));
     }
-    if (sys == SYS_SWE || sys == SYS_EULER) {
+    if (sys == SYS_SWE || sys == SYS_EULER || sys == SYS_NSE) {
         d.mm0_h0[0] = Q0[1] * Q0[1] / Q0[0];
         d.mm0_h0[1] = Q0[1] * Q0[2] / Q0[0];
         d.mm0_h0[2] = Q0[2] * Q0[2] / Q0[0];
     }
+    if (sys == SYS_RELHYDRO) {
+        d.sq_ref = std::sqrt(4.0 * Q0[0] * Q0[0] - 3.0 * (Q0[1] * Q0[1] + Q0[2] * Q0[2]));
+        d.p_ref = (d.sq_ref - Q0[0]) / 3.0;
+        d.H_ref = Q0[0] + d.p_ref;
+        d.mm0_h0[0] = Q0[1] * Q0[1] / d.H_ref;
+        d.mm0_h0[1] = Q0[1] * Q0[2] / d.H_ref;
+        d.mm0_h0[2] = Q0[2] * Q0[2] / d.H_ref;
+    }
+    d.cs2_phys = cs_phys * cs_phys;
     if (sys == SYS_EULER) {
         d.p_ref = (gamma - 1.0) * (Q0[3] - 0.5 * (Q0[1] * Q0[1] + Q0[2] * Q0[2]) / Q0[0]);
         d.H_ref = Q0[3] + d.p_ref;
@@ -781,6 +791,8 @@ KParams<R> lbm_state_impl::kparams(double t_half) const
     for (int k = 0; k < LBM_MAXK; ++k) p.phys.Q0[k] = (R)d.Q0[k];
     p.phys.g = (R)d.g;
     p.phys.c_light = (R)d.c_light;
+    p.phys.cs2_phys = (R)d.cs2_phys;
+    p.phys.sq_ref = (R)d.sq_ref;
     for (int j = 0; j < 3; ++j) {
         p.phys.mm0_h0[j] = (R)d.mm0_h0[j];
         p.phys.Hu_ref[j] = (R)d.Hu_ref[j];
@@ -979,6 +991,14 @@ const Launchers *lbm_launchers(int sys, int lat, int storage)
     case SYS_ALLENCAHN:
         if (lat == LAT_D2Q5) return by_storage<SysAllenCahn, D2Q5>(storage);
         if (lat == LAT_D2Q9) return by_storage<SysAllenCahn, D2Q9>(storage);
+        break;
+    case SYS_RELHYDRO:
+        if (lat == LAT_D2Q5) return by_storage<SysRelHydro, D2Q5>(storage);
+        if (lat == LAT_D2Q9) return by_storage<SysRelHydro, D2Q9>(storage);
+        break;
+    case SYS_NSE:
+        if (lat == LAT_D2Q5) return by_storage<SysNSE, D2Q5>(storage);
+        if (lat == LAT_D2Q9) return by_storage<SysNSE, D2Q9>(storage);
         break;
     }
     return nullptr;

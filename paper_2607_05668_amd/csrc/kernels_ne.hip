@@ -459,6 +459,14 @@ const Launchers *lbm_launchers_ne(int sys, int lat)
         if (lat == LAT_D2Q5) return ImplNE<SysAllenCahn, D2Q5>::get();
         if (lat == LAT_D2Q9) return ImplNE<SysAllenCahn, D2Q9>::get();
         break;
+    case SYS_RELHYDRO:
+        if (lat == LAT_D2Q5) return ImplNE<SysRelHydro, D2Q5>::get();
+        if (lat == LAT_D2Q9) return ImplNE<SysRelHydro, D2Q9>::get();
+        break;
+    case SYS_NSE:
+        if (lat == LAT_D2Q5) return ImplNE<SysNSE, D2Q5>::get();
+        if (lat == LAT_D2Q9) return ImplNE<SysNSE, D2Q9>::get();
+        break;
     }
     return nullptr;
 }

@@ -41,6 +41,8 @@ int system_id(const char *s)
     if (!std::strcmp(s, "euler2d")) return SYS_EULER;
     if (!std::strcmp(s, "maxwell2d")) return SYS_MAXWELL;
     if (!std::strcmp(s, "allencahn_trk2d")) return SYS_ALLENCAHN;
+    if (!std::strcmp(s, "relhydro2d")) return SYS_RELHYDRO;
+    if (!std::strcmp(s, "nse_trk2d")) return SYS_NSE;
     return -1;
 }
 
@@ -53,8 +55,8 @@ int lattice_id(const char *s)
     return -1;
 }
 
-const int kSysK[8] = {3, 3, 6, 17, 1, 4, 3, 3};
-const int kSysD[8] = {2, 2, 2, 3, 2, 2, 2, 2};
+const int kSysK[10] = {3, 3, 6, 17, 1, 4, 3, 3, 3, 7};
+const int kSysD[10] = {2, 2, 2, 3, 2, 2, 2, 2, 2, 2};
 const int kLatQ[3] = {5, 9, 7};
 const int kLatD[3] = {2, 2, 3};
 const double kLatCs2[3] = {1.0 / 3.0, 1.0 / 3.0, 1.0 / 4.0};
@@ -90,11 +92,16 @@ void default_reference(lbm_state *h)
     case SYS_NEOHOOKE: h->Q0[0] = 1.0; h->Q0[3] = 1.0; break;
     case SYS_NSF17: nsf_default_reference(h); break;
     case SYS_BURGERS: break;                       // u0 = 0
+    case SYS_RELHYDRO: h->Q0[0] = 3.0; h->Q0[1] = 1.2; h->Q0[2] = 1.2; break;
+    case SYS_NSE: h->Q0[0] = 1.0; break;
     case SYS_EULER: euler_default_reference(h); break;
     }
 }
 
-bool has_trackers(int sys) { return sys == SYS_ADVDIFF || sys == SYS_NSF17 || sys == SYS_ALLENCAHN; }
+bool has_trackers(int sys)
+{
+    return sys == SYS_ADVDIFF || sys == SYS_NSF17 || sys == SYS_ALLENCAHN || sys == SYS_NSE;
+}
 
 size_t arith_bytes(const lbm_state *h) { return h->storage == LBM_F64 ? 8 : 4; }
 
@@ -215,6 +222,21 @@ int lbm_set_param(lbm_state *h, const char *name, double v)
         if (n == "c") {
             if (!(v > 0)) return fail(h, LBM_EINVAL, "c must be positive");
             h->c_light = v;
+            return LBM_OK;
+        }
+        break;
+    case SYS_RELHYDRO:
+        break;
+    case SYS_NSE:
+        if (n == "cs_phys") {
+            if (!(v > 0)) return fail(h, LBM_EINVAL, "cs_phys must be positive");
+            h->cs_phys = v;
+            return LBM_OK;
+        }
+        if (n == "mu") { h->mu = v; return LBM_OK; }
+        if (n == "g_tau") {
+            if (!(v > 0)) return fail(h, LBM_EINVAL, "g_tau must be positive");
+            h->g_tau = v;
             return LBM_OK;
         }
         break;

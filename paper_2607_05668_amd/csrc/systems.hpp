@@ -32,6 +32,8 @@ struct Phys {
     R tau_ref[9];         // viscous stress of the reference trackers
     R rho0, mu_s, lam_s;  // elasticity
     R c_light;            // Maxwell wave speed
+    R cs2_phys;           // weakly compressible NSE: artificial sound speed squared
+    R sq_ref;             // ultrarelativistic: sqrt(4 E0^2 - 3 |S0|^2)
     R H0[4];              // F0 - I (reference deformation minus identity)
     R P0[4];              // first Piola-Kirchhoff stress at F0
 };
@@ -245,6 +247,115 @@ struct SysAllenCahn {
     __host__ __device__ static R max_speed(const Phys<R> &p, const R *)
     {
         return sqrt(p.nu * p.inv_tau_grad);
+    }
+};
+
+// ------------------------------------------------------------ RELHYDRO --
+// Ideal ultrarelativistic fluid, c = 1, p = e/3 (Sec. 3): Q = (E, S),
+// p = (sqrt(4 E^2 - 3 |S|^2) - E) / 3, v = S / (E + p), Phi_E = S,
+// Phi_S = S (x) v + p I = S (x) S / H + p I with H = E + p, no source.
+// Fluctuation form: d sqrt = (4 dE (2 E0 + dE) - 3 dS.(2 S0 + dS)) /
+// (sqrt + sqrt0), dp = (d sqrt - dE) / 3, S (x) S / H through dquot.
+struct SysRelHydro {
+    static constexpr int K = 3, D = 2, id = 8;
+    static constexpr bool precise = true;    // float-float equilibrium in single precision
+    static constexpr bool compensated = true;   // two-sum moments dQ = hi + lo
+    static constexpr bool tracker(int) { return false; }
+
+    template <class S, class R>
+    __host__ __device__ static void flux_delta(const Phys<R> &p, const S *dQ, S dPhi[][D])
+    {
+        const R E0 = p.Q0[0], Sx0 = p.Q0[1], Sy0 = p.Q0[2];
+        const S dE = dQ[0], dSx = dQ[1], dSy = dQ[2];
+        const S E = dE + E0, Sx = dSx + Sx0, Sy = dSy + Sy0;
+        const S sq = lbm_sqrt(E * E * R(4) - (Sx * Sx + Sy * Sy) * R(3));
+        const S num = dE * (dE + R(2) * E0) * R(4) - (dSx * (dSx + R(2) * Sx0) + dSy * (dSy + R(2) * Sy0)) * R(3);
+        const S dp = (num / (sq + p.sq_ref) - dE) * R(1.0 / 3.0);
+        const S dH = dE + dp;
+        const S H = dH + p.H_ref;
+        const S xy = dquot(Sx0, Sy0, p.mm0_h0[1], dSx, dSy, H, dH);
+        dPhi[0][0] = dSx;
+        dPhi[0][1] = dSy;
+        dPhi[1][0] = dquot(Sx0, Sx0, p.mm0_h0[0], dSx, dSx, H, dH) + dp;
+        dPhi[1][1] = xy;
+        dPhi[2][0] = xy;
+        dPhi[2][1] = dquot(Sy0, Sy0, p.mm0_h0[2], dSy, dSy, H, dH) + dp;
+    }
+
+    template <class S, class R>
+    __host__ __device__ static void source(const Phys<R> &, const S *, const R *, S *Sk)
+    {
+#pragma unroll
+        for (int k = 0; k < K; ++k) Sk[k] = S(R(0));
+    }
+
+    // characteristic speeds of the massless gas never exceed c = 1
+    template <class R>
+    __host__ __device__ static R max_speed(const Phys<R> &, const R *)
+    {
+        return R(1);
+    }
+};
+
+// ----------------------------------------------------------------- NSE --
+// Weakly compressible Navier-Stokes with a momentum-gradient tracker
+// (Sec. 3, incompressible limit): Q = (rho, m0, m1, G00, G01, G10, G11),
+// G_ab ~ d_b m_a, Phi_m = m (x) m / rho + rho cs^2 I - mu (G + G^T) / rho,
+// Phi_{G_ab, c} = G_ab m_c / rho - delta_bc m_a / tau_grad,
+// S_G = -G / tau_grad.  Quotients through dquot; the reference ratios of
+// the tracker rows are wave-uniform and formed in the kernel.
+struct SysNSE {
+    static constexpr int K = 7, D = 2, id = 9;
+    static constexpr bool precise = true;    // float-float equilibrium in single precision
+    static constexpr bool compensated = true;   // two-sum moments dQ = hi + lo
+    static constexpr bool tracker(int k) { return k >= 3; }
+
+    template <class S, class R>
+    __host__ __device__ static void flux_delta(const Phys<R> &p, const S *dQ, S dPhi[][D])
+    {
+        const R r0 = p.Q0[0];
+        const R m0[2] = {p.Q0[1], p.Q0[2]};
+        const S dr = dQ[0];
+        const S dm[2] = {dQ[1], dQ[2]};
+        const S r = dr + r0;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            dPhi[0][c] = dm[c];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const int q = a + c;                  // (0,0) -> 0, (0,1)/(1,0) -> 1, (1,1) -> 2
+                const S conv = dquot(m0[a], m0[c], p.mm0_h0[q], dm[a], dm[c], r, dr);
+                const R X0 = p.Q0[3 + 2 * a + c] + p.Q0[3 + 2 * c + a];
+                const S dX = dQ[3 + 2 * a + c] + dQ[3 + 2 * c + a];
+                const S visc = (dX - dr * (X0 / r0)) / r;
+                dPhi[1 + a][c] = (a == c) ? conv + dr * p.cs2_phys - visc * p.mu : conv - visc * p.mu;
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const R G0 = p.Q0[3 + 2 * a + b];
+                    const S tr = dquot(G0, m0[c], G0 * m0[c] / r0, dQ[3 + 2 * a + b], dm[c], r, dr);
+                    dPhi[3 + 2 * a + b][c] = (b == c) ? tr - dm[a] * p.inv_tau_grad : tr;
+                }
+        }
+    }
+
+    template <class S, class R>
+    __host__ __device__ static void source(const Phys<R> &p, const S *dQ, const R *, S *Sk)
+    {
+        Sk[0] = Sk[1] = Sk[2] = S(R(0));
+#pragma unroll
+        for (int k = 3; k < K; ++k) Sk[k] = (dQ[k] + p.Q0[k]) * (-p.inv_tau_grad);
+    }
+
+    // bound: |u| + cs + sqrt(2 mu / (rho tau_grad)) (acoustic plus the
+    // tracker-coupled viscous modes)
+    template <class R>
+    __host__ __device__ static R max_speed(const Phys<R> &p, const R *Q)
+    {
+        const R ux = Q[1] / Q[0], uy = Q[2] / Q[0];
+        return sqrt(ux * ux + uy * uy) + sqrt(p.cs2_phys) + sqrt(R(2) * p.mu * p.inv_tau_grad / Q[0]);
     }
 };
 

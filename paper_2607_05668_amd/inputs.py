@@ -141,6 +141,10 @@ PRESETS = {
                           "acoustic", 0.2, 0.2, None, {"c": 1.0}),
     "allencahn2048": Preset("allencahn2048", "allencahn_trk2d", "D2Q5", 2048, "f32", 100,
                             "diffusive", 1.9, 50.0, 6.0, {"nu": 0.01, "R": 1.0}),
+    "relhydro2048": Preset("relhydro2048", "relhydro2d", "D2Q5", 2048, "f32", 100,
+                           "acoustic", 0.2, 0.2, None, {}),
+    "nse2048": Preset("nse2048", "nse_trk2d", "D2Q5", 2048, "f32", 100,
+                      "diffusive", 2.0, 90.0, 6.0, {"cs_phys": 1.0, "mu": 0.01}),
 }
 
 # Seeds of the random fields.
@@ -230,6 +234,32 @@ def allencahn_initial(n: int, amp: float = 0.7):
     k = 2.0 * math.pi
     phi = amp * np.sin(k * X) * np.cos(k * Y)
     return np.stack([phi, amp * k * np.cos(k * X) * np.cos(k * Y), -amp * k * np.sin(k * X) * np.sin(k * Y)])
+
+
+def relhydro_initial(n: int):
+    """The paper's ultrarelativistic profile at t = 0: E = 3 + 0.4 sin sin,
+    S = (1.2, 1.2), [3, n, n]."""
+    X, Y = grid2(n)
+    k = 2.0 * math.pi
+    E = 3.0 + 0.4 * np.sin(k * X) * np.sin(k * Y)
+    return np.stack([E, np.full_like(E, 1.2), np.full_like(E, 1.2)])
+
+
+def nse_initial(n: int, U: float = 0.1):
+    """The paper's Taylor-Green state at t = 0 (rho0 = cs = 1): rho = 1 + p,
+    p = -U^2 (cos 2kx + cos 2ky) / 4, m = rho u, and the exact momentum
+    gradients d_b m_a as tracker fields, [7, n, n]."""
+    X, Y = grid2(n)
+    k = 2.0 * math.pi
+    u = -U * np.cos(k * X) * np.sin(k * Y)
+    v = U * np.sin(k * X) * np.cos(k * Y)
+    rho = 1.0 - 0.25 * U * U * (np.cos(2 * k * X) + np.cos(2 * k * Y))
+    drx = 0.5 * U * U * k * np.sin(2 * k * X)
+    dry = 0.5 * U * U * k * np.sin(2 * k * Y)
+    dux, duy = U * k * np.sin(k * X) * np.sin(k * Y), -U * k * np.cos(k * X) * np.cos(k * Y)
+    dvx, dvy = U * k * np.cos(k * X) * np.cos(k * Y), -U * k * np.sin(k * X) * np.sin(k * Y)
+    return np.stack([rho, rho * u, rho * v, drx * u + rho * dux, dry * u + rho * duy,
+                     drx * v + rho * dvx, dry * v + rho * dvy])
 
 
 def neohooke_initial(n: int, seeds=SEED_DISPLACEMENT):

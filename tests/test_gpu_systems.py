@@ -132,3 +132,34 @@ def test_allencahn_matches_oracle(lattice, shape, storage, tol):
     print("rel L2", {k: f"{v:.3e}" for k, v in errs.items()})
     for k, v in errs.items():
         assert v <= tol, k
+
+
+@pytest.mark.parametrize("lattice,shape,storage,tol", [
+    ("D2Q5", (128, 128), "f32", 1e-6), ("D2Q9", (48, 80), "f32", 1e-6),
+    ("D2Q5", (64, 64), "f64", 1e-12), ("D2Q5", (128, 128), "f16ne", 1e-3)])
+def test_relhydro_matches_oracle(lattice, shape, storage, tol):
+    """The paper's ultrarelativistic profile at t = 0 (E fluctuation about 3,
+    S = (1.2, 1.2)), recipe f = 0.2, tau_R = 0.2, unforced."""
+    print(f"relhydro2d {lattice} {storage} {shape} 300 steps", flush=True)
+    fQ, _ = mms.relhydro_paper()
+    Qg, Qo = run_pair("relhydro2d", lattice, shape, 0.2, 0.2, 300, storage, {}, fQ)
+    errs = {"E": rel(Qg[0], Qo[0]), "S": rel(Qg[1:], Qo[1:])}
+    print("rel L2", {k: f"{v:.3e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= tol, k
+
+
+@pytest.mark.parametrize("lattice,shape,storage,tol", [
+    ("D2Q5", (64, 64), "f32", 1e-6), ("D2Q9", (40, 64), "f32", 1e-6), ("D2Q5", (64, 64), "f64", 1e-12)])
+def test_nse_matches_oracle(lattice, shape, storage, tol):
+    """The paper's Taylor-Green state at t = 0 with exact momentum-gradient
+    trackers (rho0 = cs = 1, U = 0.1, mu = 0.01), diffusive recipe f = 2,
+    tau_R = 90 (single) / 50 (double), g_tau = 6, unforced."""
+    print(f"nse_trk2d {lattice} {storage} {shape} 500 steps", flush=True)
+    fQ, _ = mms.nse_paper()
+    Qg, Qo = run_pair("nse_trk2d", lattice, shape, 2.0, 50.0 if storage == "f64" else 90.0, 500, storage,
+                      {"cs_phys": 1.0, "mu": 0.01, "g_tau": 6.0}, fQ, diffusive=True)
+    errs = {"rho": rel(Qg[0], Qo[0]), "m": rel(Qg[1:3], Qo[1:3]), "G": rel(Qg[3:], Qo[3:])}
+    print("rel L2", {k: f"{v:.3e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= tol, k

@@ -1001,7 +1001,8 @@ def test_relhydro_mms_convergence():
 @pytest.mark.slow
 def test_relhydro_mms_matches_printed_table():
     """N = 64..512: N = 512 errors and LSQ orders against the printed FP64 rows
-    (E 2.1354e-6 / 2.00, S 6.3943e-6 / 2.00)."""
+    (E 2.1354e-6 / 2.00, S 6.3943e-6 / 2.00; the oracle reproduces both errors
+    to five digits)."""
     g = _gold("mms_printed.json")
     ns = (64, 128, 256, 512)
     e = _relhydro_mms_errors(ns)
