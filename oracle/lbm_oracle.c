@@ -33,11 +33,11 @@
 #define MAXQ 9
 
 enum { SYS_ADVDIFF = 0, SYS_SWE = 1, SYS_NEOHOOKE = 2, SYS_NSF17 = 3, SYS_BURGERS = 4, SYS_EULER = 5,
-       SYS_MAXWELL = 6, SYS_ALLENCAHN = 7, SYS_RELHYDRO = 8, SYS_NSE = 9 };
+       SYS_MAXWELL = 6, SYS_ALLENCAHN = 7, SYS_RELHYDRO = 8, SYS_NSE = 9, SYS_CNSF2D = 10 };
 enum { LAT_D2Q5 = 0, LAT_D2Q9 = 1, LAT_D3Q7 = 2 };
 enum {
     P_G = 0, P_AX, P_AY, P_AZ, P_NU, P_R, P_TAUG, P_GAMMA, P_MU, P_KAPPA,
-    P_RHO0, P_MUS, P_LAMS, P_CLIGHT, P_CSPHYS, P_COUNT
+    P_RHO0, P_MUS, P_LAMS, P_CLIGHT, P_CSPHYS, P_RGAS, P_COUNT
 };
 
 typedef struct {
@@ -105,6 +105,7 @@ static int system_K(int sys)
     case SYS_ALLENCAHN: return 3;
     case SYS_RELHYDRO: return 3;
     case SYS_NSE: return 7;
+    case SYS_CNSF2D: return 12;
     }
     return 0;
 }

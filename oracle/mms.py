@@ -25,6 +25,8 @@ Cases:
 * ``relhydro_paper`` -- the paper's ultrarelativistic-fluid MMS.
 * ``nse_paper``  -- the paper's weakly compressible NSE (Taylor-Green) MMS,
   nondimensional, trackers exact.
+* ``cnsf2d_paper`` -- the paper's 2D compressible NSF MMS (Mach 3 / 2),
+  trackers exact.
 * ``nsf17``      -- the 3D compressible NSF manufactured solution with the
   shapes of the paper's homogenized-NSF MMS (porosity 1), conserved rows
   forced; tracker rows are forced only when ``force_trackers`` is set.
@@ -226,6 +228,56 @@ def nse_paper(rho0=1.0, cs=1.0, U=0.1, mu=0.01):
     Q = [rho, m0, m1, G[0][0], G[0][1], G[1][0], G[1][1]]
     res = [sp.diff(Q[k], T) + _div(Phi[k], (X, Y)) for k in range(3)] + [sp.Integer(0)] * 4
     fQ = sp.lambdify((X, Y, T), Q, "numpy")
+    fS = sp.lambdify((X, Y, T), res, "numpy", cse=True)
+    return _wrap2(fQ), _wrap2(fS)
+
+
+# ------------------------------------------------------------- CNSF 2D ----
+def cnsf2d_exact_exprs(rho0=1.0, cs=1.0, gamma=1.4):
+    """The paper's 2D compressible NSF MMS (supplement): per-axis Mach 3 and 2
+    background, fluctuations 0.20 rho0, 0.20 cs, 0.15 cs and cs^2 d rho +
+    0.20 p0 in the printed modes, p0 = rho0 cs^2 / gamma."""
+    r0, c, gm = sp.Float(rho0), sp.Float(cs), sp.Float(gamma)
+    p0 = r0 * c ** 2 / gm
+    drho = sp.Rational(1, 5) * r0 * sp.sin(PI2 * X) * sp.cos(PI2 * Y) * sp.cos(T)
+    du = sp.Rational(1, 5) * c * sp.cos(PI2 * X) * sp.sin(PI2 * Y) * sp.sin(T)
+    dv = sp.Rational(3, 20) * c * sp.sin(PI2 * X) * sp.sin(PI2 * Y) * sp.cos(T)
+    dp = c ** 2 * drho + sp.Rational(1, 5) * p0 * sp.cos(PI2 * X) * sp.sin(PI2 * Y) * sp.sin(T)
+    rho = r0 + drho
+    u, v = 3 * c + du, 2 * c + dv
+    p = p0 + dp
+    E = p / (gm - 1) + rho * (u ** 2 + v ** 2) / 2
+    return [rho, rho * u, rho * v, E]
+
+
+@functools.lru_cache(maxsize=None)
+def cnsf2d_paper(mu, kappa, R=1.0, gamma=1.4, rho0=1.0, cs=1.0):
+    """(exact(x, y, t) -> [12, ...], forcing -> [12, ...]): conserved rows
+    forced with the flux at the exact trackers, tracker rows not forced."""
+    Qc = cnsf2d_exact_exprs(rho0, cs, gamma)
+    G = [sp.diff(Qc[j], v) for j in (0, 1, 2, 3) for v in (X, Y)]
+    Q = Qc + G
+    gm, muf, Kf, Rf = sp.Float(gamma), sp.Float(mu), sp.Float(kappa), sp.Float(R)
+    rho, m0, m1, E = Qc
+    u = [m0 / rho, m1 / rho]
+    p = (gm - 1) * (E - (m0 * u[0] + m1 * u[1]) / 2)
+    Gr = [G[0], G[1]]
+    Gm = [[G[2], G[3]], [G[4], G[5]]]
+    GE = [G[6], G[7]]
+    du = [[(Gm[a][b] - u[a] * Gr[b]) / rho for b in range(2)] for a in range(2)]
+    div = du[0][0] + du[1][1]
+    tau = [[muf * (du[a][b] + du[b][a] - (sp.Rational(2, 3) * div if a == b else 0)) for b in range(2)]
+           for a in range(2)]
+    gT = []
+    for b in range(2):
+        gp = (gm - 1) * (GE[b] - (u[0] * Gm[0][b] + u[1] * Gm[1][b]) + (u[0] ** 2 + u[1] ** 2) * Gr[b] / 2)
+        gT.append((gp - p * Gr[b] / rho) / (Rf * rho))
+    Phi = [[m0, m1]]
+    for a in range(2):
+        Phi.append([(m0, m1)[a] * u[c] + (p if a == c else 0) - tau[a][c] for c in range(2)])
+    Phi.append([(E + p) * u[c] - (tau[c][0] * u[0] + tau[c][1] * u[1]) - Kf * gT[c] for c in range(2)])
+    res = [sp.diff(Qc[k], T) + _div(Phi[k], (X, Y)) for k in range(4)] + [sp.Integer(0)] * 8
+    fQ = sp.lambdify((X, Y, T), Q, "numpy", cse=True)
     fS = sp.lambdify((X, Y, T), res, "numpy", cse=True)
     return _wrap2(fQ), _wrap2(fS)
 

@@ -1047,3 +1047,110 @@ def test_nse_mms_pairwise_order():
     for i, k in enumerate(("rho", "m")):
         assert 2.6 < math.log2(a[i] / b[i]) < 3.0, k
         assert 2 ** 4.4 < b[i] / g[f"nse_double_{k}_relL2_N512"] < 2 ** 5.0, k
+
+
+# ------------------------------------------------------------ CNSF 2D ----
+def test_cnsf2d_flux_matches_printed_expansion():
+    """Supplement, compressible NSF: the compiler-expanded momentum and energy
+    fluxes (viscous stress and Fourier heat flux through the chain rule on
+    the conserved-field trackers) and the tracker rows, at random states
+    (gamma = 1.4, mu = 0.013, K = 0.07, R = 0.9).  The printed state order
+    (Q4 = G_(rho u),1,0 ... Q11 = G_(rho u),0,1) is mapped to this oracle's."""
+    gm, mu, K, R = 1.4, 0.013, 0.07, 0.9
+    o = _mk("cnsf_trk2d", "D2Q5", {"gamma": gm, "mu": mu, "kappa": K, "R_gas": R}, [1, 3, 2, 9] + [0] * 8, 6.0, 4,
+            lam=0.02)
+    tg = o.params["tau_grad"]
+    rng = np.random.default_rng(51)
+    g = gm
+    for _ in range(20):
+        r = rng.uniform(0.8, 1.2)
+        m0, m1 = rng.uniform(-3, 3, 2)
+        E = rng.uniform(8, 12)
+        Gr0, Gr1, Gm00, Gm01, Gm10, Gm11, GE0, GE1 = rng.uniform(-1, 1, 8)
+        F = o.flux([r, m0, m1, E, Gr0, Gr1, Gm00, Gm01, Gm10, Gm11, GE0, GE1])
+        P10 = (E * g - E + 4 * Gr0 * mu * m0 / (3 * r * r) - 2 * Gr1 * mu * m1 / (3 * r * r) - 4 * Gm00 * mu / (3 * r)
+               + 2 * Gm11 * mu / (3 * r) - g * m0 ** 2 / (2 * r) - g * m1 ** 2 / (2 * r) + 3 * m0 ** 2 / (2 * r)
+               + m1 ** 2 / (2 * r))
+        P11 = Gr0 * mu * m1 / r ** 2 + Gr1 * mu * m0 / r ** 2 - Gm01 * mu / r - Gm10 * mu / r + m0 * m1 / r
+        P21 = (E * g - E - 2 * Gr0 * mu * m0 / (3 * r * r) + 4 * Gr1 * mu * m1 / (3 * r * r) + 2 * Gm00 * mu / (3 * r)
+               - 4 * Gm11 * mu / (3 * r) - g * m0 ** 2 / (2 * r) - g * m1 ** 2 / (2 * r) + m0 ** 2 / (2 * r)
+               + 3 * m1 ** 2 / (2 * r))
+        P30 = (E * Gr0 * K * g / (R * r * r) - E * Gr0 * K / (R * r * r) + E * g * m0 / r - GE0 * K * g / (R * r)
+               + GE0 * K / (R * r) - Gr0 * K * g * m0 ** 2 / (R * r ** 3) - Gr0 * K * g * m1 ** 2 / (R * r ** 3)
+               + Gr0 * K * m0 ** 2 / (R * r ** 3) + Gr0 * K * m1 ** 2 / (R * r ** 3) + 4 * Gr0 * mu * m0 ** 2 / (3 * r ** 3)
+               + Gr0 * mu * m1 ** 2 / r ** 3 + Gr1 * mu * m0 * m1 / (3 * r ** 3) + Gm00 * K * g * m0 / (R * r * r)
+               - Gm00 * K * m0 / (R * r * r) - 4 * Gm00 * mu * m0 / (3 * r * r) - Gm01 * mu * m1 / (r * r)
+               + Gm10 * K * g * m1 / (R * r * r) - Gm10 * K * m1 / (R * r * r) - Gm10 * mu * m1 / (r * r)
+               + 2 * Gm11 * mu * m0 / (3 * r * r) - g * m0 ** 3 / (2 * r * r) - g * m0 * m1 ** 2 / (2 * r * r)
+               + m0 ** 3 / (2 * r * r) + m0 * m1 ** 2 / (2 * r * r))
+        P31 = (E * Gr1 * K * g / (R * r * r) - E * Gr1 * K / (R * r * r) + E * g * m1 / r - GE1 * K * g / (R * r)
+               + GE1 * K / (R * r) + Gr0 * mu * m0 * m1 / (3 * r ** 3) - Gr1 * K * g * m0 ** 2 / (R * r ** 3)
+               - Gr1 * K * g * m1 ** 2 / (R * r ** 3) + Gr1 * K * m0 ** 2 / (R * r ** 3) + Gr1 * K * m1 ** 2 / (R * r ** 3)
+               + Gr1 * mu * m0 ** 2 / r ** 3 + 4 * Gr1 * mu * m1 ** 2 / (3 * r ** 3) + 2 * Gm00 * mu * m1 / (3 * r * r)
+               + Gm01 * K * g * m0 / (R * r * r) - Gm01 * K * m0 / (R * r * r) - Gm01 * mu * m0 / (r * r)
+               - Gm10 * mu * m0 / (r * r) + Gm11 * K * g * m1 / (R * r * r) - Gm11 * K * m1 / (R * r * r)
+               - 4 * Gm11 * mu * m1 / (3 * r * r) - g * m0 ** 2 * m1 / (2 * r * r) - g * m1 ** 3 / (2 * r * r)
+               + m0 ** 2 * m1 / (2 * r * r) + m1 ** 3 / (2 * r * r))
+        for (k, c), v in {(0, 0): m0, (0, 1): m1, (1, 0): P10, (1, 1): P11, (2, 0): P11, (2, 1): P21,
+                          (3, 0): P30, (3, 1): P31}.items():
+            assert F[k, c] == pytest.approx(v, rel=1e-12, abs=1e-12), (k, c)
+        # tracker rows, printed: Phi_{8,0} = G_rho,0 m0 / rho - rho / tau_grad, ...
+        x = (r, m0, m1, E)
+        G = (Gr0, Gr1, Gm00, Gm01, Gm10, Gm11, GE0, GE1)
+        for j in range(4):
+            for b in range(2):
+                for c in range(2):
+                    want = G[2 * j + b] * (m0, m1)[c] / r - (x[j] / tg if b == c else 0.0)
+                    assert F[4 + 2 * j + b, c] == pytest.approx(want, rel=1e-12, abs=1e-12)
+
+
+def test_cnsf2d_mms_fields_match_printed_expansion():
+    """Supplement, compressible NSF MMS: printed expanded conserved fields in
+    rho0, cs (SI 1.225, 340.2; Mach 3 and 2 background)."""
+    si = _gold("mms_printed.json")["cnsf2d_mms_SI"]
+    r0, c = si["rho0"], si["cs"]
+    f = sp.lambdify((mms.X, mms.Y, mms.T), mms.cnsf2d_exact_exprs(r0, c, si["gamma"]), "numpy")
+    rng = np.random.default_rng(52)
+    for x, y, t in rng.uniform(0, 1, (10, 3)):
+        sx, cx = math.sin(2 * math.pi * x), math.cos(2 * math.pi * x)
+        sy, cy = math.sin(2 * math.pi * y), math.cos(2 * math.pi * y)
+        st, ct = math.sin(t), math.cos(t)
+        rho = r0 * sx * ct * cy / 5 + r0
+        a = c * st * sy * cx / 5 + 3 * c
+        b = 3 * c * sx * sy * ct / 20 + 2 * c
+        q3 = (5 * c * c * r0 * st * sy * cx / 14 + c * c * r0 * sx * ct * cy / 2 + 25 * c * c * r0 / 14
+              + (r0 * sx * ct * cy / 10 + r0 / 2) * (b * b + a * a))
+        assert np.allclose(np.array(f(x, y, t), dtype=float), [rho, a * rho, b * rho, q3], rtol=1e-12, atol=0)
+
+
+def _cnsf2d_errors(n):
+    g = _gold("mms_printed.json")
+    rec, si = g["recipes"]["cnsf2d_double"], g["cnsf2d_mms_SI"]
+    # nondimensional reading (rho0 = cs = L = 1): mu / (rho0 cs L), (K / R) / (rho0 cs L)
+    mu = si["mu"] / (si["rho0"] * si["cs"])
+    K = si["K"] / (si["R"] * si["rho0"] * si["cs"])
+    gm = si["gamma"]
+    fQ, fS = mms.cnsf2d_paper(mu, K, 1.0, gm)
+    dx, dt, tau = oracle.recipe(n, "diffusive", rec["f"], rec["tau_r"])
+    X, Y = inputs.grid2(n)
+    o = oracle.Oracle("cnsf_trk2d", "D2Q5", (n, n), dt, dx, tau, rec["g_tau"],
+                      {"gamma": gm, "mu": mu, "kappa": K, "R_gas": 1.0},
+                      Q0=[1.0, 3.0, 2.0, 1 / gm / (gm - 1) + 6.5] + [0.0] * 8)
+    o.init(fQ(X, Y, 0.0))
+    o.step(int(round(1.0 / dt)), source=lambda t: fS(X, Y, t))
+    Qn, Qe = o.moments(), fQ(X, Y, o.t)
+    return {"rho": mms.rel_l2(Qn[0], Qe[0]), "E": mms.rel_l2(Qn[3], Qe[3]),
+            "m": math.hypot(mms.rel_l2(Qn[1], Qe[1]), mms.rel_l2(Qn[2], Qe[2]))}
+
+
+@pytest.mark.slow
+def test_cnsf2d_mms_near_second_order():
+    """Diffusive recipe f = 2, tau_R = 60, g_tau = 6, read with rho0 = cs = 1
+    (mu = 8.45e-3, K / R = 4.16e-2): the 64 -> 128 orders of rho, rho u and
+    E lie near the printed LSQ orders (oracle 1.77 - 1.86).  Magnitude
+    unpinned: carried to N = 512 at that order the oracle's errors are about
+    twice the printed ones, and no reading of the SI parameters that was
+    tried (tracker forcing, zero initial trackers) closes the gap."""
+    a, b = _cnsf2d_errors(64), _cnsf2d_errors(128)
+    for k in ("rho", "m", "E"):
+        assert 1.65 < math.log2(a[k] / b[k]) < 2.2, k
