@@ -10,7 +10,7 @@
 
 enum {
     SYS_ADVDIFF = 0, SYS_SWE = 1, SYS_NEOHOOKE = 2, SYS_NSF17 = 3, SYS_BURGERS = 4, SYS_EULER = 5,
-    SYS_MAXWELL = 6, SYS_ALLENCAHN = 7, SYS_RELHYDRO = 8, SYS_NSE = 9
+    SYS_MAXWELL = 6, SYS_ALLENCAHN = 7, SYS_RELHYDRO = 8, SYS_NSE = 9, SYS_CNSF2D = 10
 };
 enum { LAT_D2Q5 = 0, LAT_D2Q9 = 1, LAT_D3Q7 = 2 };
 
@@ -94,6 +94,7 @@ struct lbm_state_impl {
     double rho0_el = 1.0, mu_s = 1.0, lam_s = 1.0;
     double c_light = 1.0;
     double cs_phys = 1.0;
+    double R_gas = 1.0;
     int mms_on = 0;
     double mms_amp = 0.05, mms_rho0 = 1.0, mms_p0 = 1.0, mms_u0 = 0.0;
     double t0 = 0.0;

@@ -720,6 +720,7 @@ KParams<R> lbm_state_impl::kparams(double t_half) const
         if (sys == SYS_NSF17) trk = SysNSF17::tracker(k);
         if (sys == SYS_ALLENCAHN) trk = SysAllenCahn::tracker(k);
         if (sys == SYS_NSE) trk = SysNSE::tracker(k);
+        if (sys == SYS_CNSF2D) trk = SysCNSF2D::tracker(k);
         const double om = trk ? omega_t : omega_c;
         p.omega[k] = (R)om;
         p.delta[k] = (R)(2.0 - om);
@@ -773,7 +774,8 @@ KParams<R> lbm_state_impl::kparams(double t_half) const
         d.mm0_h0[2] = Q0[2] * Q0[2] / d.H_ref;
     }
     d.cs2_phys = cs_phys * cs_phys;
-    if (sys == SYS_EULER) {
+    d.inv_R_gas = 1.0 / R_gas;
+    if (sys == SYS_EULER || sys == SYS_CNSF2D) {
         d.p_ref = (gamma - 1.0) * (Q0[3] - 0.5 * (Q0[1] * Q0[1] + Q0[2] * Q0[2]) / Q0[0]);
         d.H_ref = Q0[3] + d.p_ref;
         for (int a = 0; a < 2; ++a) {
@@ -793,6 +795,7 @@ KParams<R> lbm_state_impl::kparams(double t_half) const
     p.phys.c_light = (R)d.c_light;
     p.phys.cs2_phys = (R)d.cs2_phys;
     p.phys.sq_ref = (R)d.sq_ref;
+    p.phys.inv_R_gas = (R)d.inv_R_gas;
     for (int j = 0; j < 3; ++j) {
         p.phys.mm0_h0[j] = (R)d.mm0_h0[j];
         p.phys.Hu_ref[j] = (R)d.Hu_ref[j];
@@ -999,6 +1002,10 @@ const Launchers *lbm_launchers(int sys, int lat, int storage)
     case SYS_NSE:
         if (lat == LAT_D2Q5) return by_storage<SysNSE, D2Q5>(storage);
         if (lat == LAT_D2Q9) return by_storage<SysNSE, D2Q9>(storage);
+        break;
+    case SYS_CNSF2D:
+        if (lat == LAT_D2Q5) return by_storage<SysCNSF2D, D2Q5>(storage);
+        if (lat == LAT_D2Q9) return by_storage<SysCNSF2D, D2Q9>(storage);
         break;
     }
     return nullptr;

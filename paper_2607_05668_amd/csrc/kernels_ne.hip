@@ -467,6 +467,9 @@ const Launchers *lbm_launchers_ne(int sys, int lat)
         if (lat == LAT_D2Q5) return ImplNE<SysNSE, D2Q5>::get();
         if (lat == LAT_D2Q9) return ImplNE<SysNSE, D2Q9>::get();
         break;
+    case SYS_CNSF2D:
+        if (lat == LAT_D2Q5) return ImplNE<SysCNSF2D, D2Q5>::get();
+        break;
     }
     return nullptr;
 }

@@ -43,6 +43,7 @@ int system_id(const char *s)
     if (!std::strcmp(s, "allencahn_trk2d")) return SYS_ALLENCAHN;
     if (!std::strcmp(s, "relhydro2d")) return SYS_RELHYDRO;
     if (!std::strcmp(s, "nse_trk2d")) return SYS_NSE;
+    if (!std::strcmp(s, "cnsf_trk2d")) return SYS_CNSF2D;
     return -1;
 }
 
@@ -55,8 +56,8 @@ int lattice_id(const char *s)
     return -1;
 }
 
-const int kSysK[10] = {3, 3, 6, 17, 1, 4, 3, 3, 3, 7};
-const int kSysD[10] = {2, 2, 2, 3, 2, 2, 2, 2, 2, 2};
+const int kSysK[11] = {3, 3, 6, 17, 1, 4, 3, 3, 3, 7, 12};
+const int kSysD[11] = {2, 2, 2, 3, 2, 2, 2, 2, 2, 2, 2};
 const int kLatQ[3] = {5, 9, 7};
 const int kLatD[3] = {2, 2, 3};
 const double kLatCs2[3] = {1.0 / 3.0, 1.0 / 3.0, 1.0 / 4.0};
@@ -83,6 +84,19 @@ void euler_default_reference(lbm_state *h)
     h->Q0[3] = (1.0 / h->gamma) / (h->gamma - 1.0) + 9.0;
 }
 
+// Reference state of the 2D compressible NSF system: the background of the
+// paper's manufactured solution in units rho0 = cs = 1 (Mach 3 and 2 per
+// axis): rho0 = 1, m0 = (3, 2), E0 = p0 / (gamma - 1) + 13/2, p0 = 1/gamma,
+// trackers zero.
+void cnsf2d_default_reference(lbm_state *h)
+{
+    std::memset(h->Q0, 0, sizeof h->Q0);
+    h->Q0[0] = 1.0;
+    h->Q0[1] = 3.0;
+    h->Q0[2] = 2.0;
+    h->Q0[3] = (1.0 / h->gamma) / (h->gamma - 1.0) + 6.5;
+}
+
 void default_reference(lbm_state *h)
 {
     std::memset(h->Q0, 0, sizeof h->Q0);
@@ -94,13 +108,14 @@ void default_reference(lbm_state *h)
     case SYS_BURGERS: break;                       // u0 = 0
     case SYS_RELHYDRO: h->Q0[0] = 3.0; h->Q0[1] = 1.2; h->Q0[2] = 1.2; break;
     case SYS_NSE: h->Q0[0] = 1.0; break;
+    case SYS_CNSF2D: cnsf2d_default_reference(h); break;
     case SYS_EULER: euler_default_reference(h); break;
     }
 }
 
 bool has_trackers(int sys)
 {
-    return sys == SYS_ADVDIFF || sys == SYS_NSF17 || sys == SYS_ALLENCAHN || sys == SYS_NSE;
+    return sys == SYS_ADVDIFF || sys == SYS_NSF17 || sys == SYS_ALLENCAHN || sys == SYS_NSE || sys == SYS_CNSF2D;
 }
 
 size_t arith_bytes(const lbm_state *h) { return h->storage == LBM_F64 ? 8 : 4; }
@@ -226,6 +241,26 @@ int lbm_set_param(lbm_state *h, const char *name, double v)
         }
         break;
     case SYS_RELHYDRO:
+        break;
+    case SYS_CNSF2D:
+        if (n == "gamma") {
+            if (!(v > 1)) return fail(h, LBM_EINVAL, "gamma must exceed 1");
+            h->gamma = v;
+            if (!h->q0_set) cnsf2d_default_reference(h);
+            return LBM_OK;
+        }
+        if (n == "mu") { h->mu = v; return LBM_OK; }
+        if (n == "kappa") { h->kappa = v; return LBM_OK; }
+        if (n == "R_gas") {
+            if (!(v > 0)) return fail(h, LBM_EINVAL, "R_gas must be positive");
+            h->R_gas = v;
+            return LBM_OK;
+        }
+        if (n == "g_tau") {
+            if (!(v > 0)) return fail(h, LBM_EINVAL, "g_tau must be positive");
+            h->g_tau = v;
+            return LBM_OK;
+        }
         break;
     case SYS_NSE:
         if (n == "cs_phys") {

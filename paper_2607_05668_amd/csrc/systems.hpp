@@ -34,6 +34,7 @@ struct Phys {
     R c_light;            // Maxwell wave speed
     R cs2_phys;           // weakly compressible NSE: artificial sound speed squared
     R sq_ref;             // ultrarelativistic: sqrt(4 E0^2 - 3 |S0|^2)
+    R inv_R_gas;          // 2D compressible NSF: 1 / R (T = p / (R rho))
     R H0[4];              // F0 - I (reference deformation minus identity)
     R P0[4];              // first Piola-Kirchhoff stress at F0
 };
@@ -356,6 +357,118 @@ struct SysNSE {
     {
         const R ux = Q[1] / Q[0], uy = Q[2] / Q[0];
         return sqrt(ux * ux + uy * uy) + sqrt(p.cs2_phys) + sqrt(R(2) * p.mu * p.inv_tau_grad / Q[0]);
+    }
+};
+
+// ------------------------------------------------------------- CNSF 2D --
+// 2D compressible Navier-Stokes-Fourier with conserved-field gradient
+// trackers (Sec. 3): Q = (rho, m0, m1, E, Grho_0, Grho_1, Gm_00, Gm_01,
+// Gm_10, Gm_11, GE_0, GE_1), Gx_b ~ d_b x.  Velocity and temperature
+// gradients by the chain rule (grad u_ab = (Gm_ab - u_a Grho_b) / rho,
+// grad T from grad p and Grho), tau = mu (grad u + grad u^T - 2/3 div u I),
+// Phi_m = m (x) u + p I - tau, Phi_E = (E + p) u - tau . u - K grad T,
+// tracker rows Gx (x) u - I x / tau_grad, S_G = -G / tau_grad.
+// Fluctuation form as for the 3D cascade: du = (dm - drho u0) / rho,
+// d(a u_c) = da u_c + a0 du_c; the viscous and heat terms, small where the
+// trackers are small, as value minus reference value.
+struct SysCNSF2D {
+    static constexpr int K = 12, D = 2, id = 10;
+    static constexpr bool precise = false;   // plain exact-moment equilibrium (VALU budget)
+    static constexpr bool compensated = true;   // two-sum moments dQ = hi + lo
+    static constexpr bool tracker(int k) { return k >= 4; }
+
+    // viscous stress tau and temperature gradient of an absolute state
+    template <class S, class R>
+    __host__ __device__ static void diffusive(const Phys<R> &p, const S &rho, const S *u, const S &pr, const S *Q,
+                                              S tau[2][2], S *gT)
+    {
+        S du[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) du[a][b] = (Q[6 + 2 * a + b] - u[a] * Q[4 + b]) / rho;
+        const S div = du[0][0] + du[1][1];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                tau[a][b] = (a == b) ? (du[a][b] + du[b][a] - div * R(2.0 / 3.0)) * p.mu
+                                     : (du[a][b] + du[b][a]) * p.mu;
+        const S ku = (u[0] * u[0] + u[1] * u[1]) * R(0.5);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const S gp = (Q[10 + b] - (u[0] * Q[6 + b] + u[1] * Q[8 + b]) + ku * Q[4 + b]) * (p.gamma - R(1));
+            gT[b] = (gp - pr * Q[4 + b] / rho) * p.inv_R_gas / rho;
+        }
+    }
+
+    template <class S, class R>
+    __host__ __device__ static void flux_delta(const Phys<R> &p, const S *dQ, S dPhi[][D])
+    {
+        const S drho = dQ[0];
+        const S rho = drho + p.Q0[0];
+        const S irho = R(1) / rho;
+        S u[2], du[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            du[a] = (dQ[1 + a] - drho * p.u_ref[a]) * irho;
+            u[a] = du[a] + p.u_ref[a];
+        }
+        const S dk = (rho * (du[0] * (du[0] + R(2) * p.u_ref[0]) + du[1] * (du[1] + R(2) * p.u_ref[1]))
+                      + drho * (p.u_ref[0] * p.u_ref[0] + p.u_ref[1] * p.u_ref[1])) * R(0.5);
+        const S dp = (dQ[3] - dk) * (p.gamma - R(1));
+        const S pr = dp + p.p_ref;
+        // absolute tracker values and the diffusive terms at Q and at Q0
+        S Qa[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) Qa[k] = dQ[k] + p.Q0[k];
+        S tau[2][2], gT[2];
+        diffusive<S, R>(p, rho, u, pr, Qa, tau, gT);
+        R tau0[2][2], gT0[2];
+        const R u0[2] = {p.u_ref[0], p.u_ref[1]};
+        diffusive<R, R>(p, p.Q0[0], u0, p.p_ref, p.Q0, tau0, gT0);
+        const S dH = dQ[3] + dp;                          // d(E + p)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            dPhi[0][c] = dQ[1 + c];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                S v = dQ[1 + a] * u[c] + du[c] * p.Q0[1 + a] - (tau[a][c] - tau0[a][c]);
+                if (a == c) v = v + dp;
+                dPhi[1 + a][c] = v;
+            }
+            const S tu = (tau[c][0] - tau0[c][0]) * u[0] + (tau[c][1] - tau0[c][1]) * u[1]
+                         + du[0] * tau0[c][0] + du[1] * tau0[c][1];
+            dPhi[3][c] = dH * u[c] + du[c] * p.H_ref - tu - (gT[c] - gT0[c]) * p.kappa;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const int k = 4 + 2 * j + b;
+                    S v = dQ[k] * u[c] + du[c] * p.Q0[k];
+                    if (b == c) v = v - dQ[j] * p.inv_tau_grad;
+                    dPhi[k][c] = v;
+                }
+        }
+    }
+
+    template <class S, class R>
+    __host__ __device__ static void source(const Phys<R> &p, const S *dQ, const R *, S *Sk)
+    {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Sk[k] = S(R(0));
+#pragma unroll
+        for (int k = 4; k < K; ++k) Sk[k] = (dQ[k] + p.Q0[k]) * (-p.inv_tau_grad);
+    }
+
+    // |u| + adiabatic sound speed of the conserved (Euler) subsystem
+    template <class R>
+    __host__ __device__ static R max_speed(const Phys<R> &p, const R *Q)
+    {
+        const R rho = Q[0], u0 = Q[1] / rho, u1 = Q[2] / rho;
+        const R pr = (p.gamma - R(1)) * (Q[3] - R(0.5) * rho * (u0 * u0 + u1 * u1));
+        const R c2 = p.gamma * pr / rho;
+        return sqrt(u0 * u0 + u1 * u1) + sqrt(c2 > R(0) ? c2 : R(0));
     }
 };
 

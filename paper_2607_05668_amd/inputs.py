@@ -145,6 +145,10 @@ PRESETS = {
                            "acoustic", 0.2, 0.2, None, {}),
     "nse2048": Preset("nse2048", "nse_trk2d", "D2Q5", 2048, "f32", 100,
                       "diffusive", 2.0, 90.0, 6.0, {"cs_phys": 1.0, "mu": 0.01}),
+    "cnsf2048": Preset("cnsf2048", "cnsf_trk2d", "D2Q5", 2048, "f32", 100,
+                       "diffusive", 2.0, 60.0, 6.0,
+                       {"gamma": 1.4, "mu": 3.52 / (1.225 * 340.2), "kappa": 4980.0 / (287.0 * 1.225 * 340.2),
+                        "R_gas": 1.0}),
 }
 
 # Seeds of the random fields.
@@ -260,6 +264,28 @@ def nse_initial(n: int, U: float = 0.1):
     dvx, dvy = U * k * np.cos(k * X) * np.cos(k * Y), -U * k * np.sin(k * X) * np.sin(k * Y)
     return np.stack([rho, rho * u, rho * v, drx * u + rho * dux, dry * u + rho * duy,
                      drx * v + rho * dvx, dry * v + rho * dvy])
+
+
+def cnsf2d_initial(n: int, gamma: float = 1.4):
+    """The paper's 2D compressible NSF state at t = 0 in units rho0 = cs = 1:
+    rho = 1 + 0.2 sin(2 pi x) cos(2 pi y), u = 3, v = 2 + 0.15 sin sin,
+    p = 1/gamma + (rho - 1), conserved fields and their analytic gradients
+    (rho, m0, m1, E, G_rho, G_m0, G_m1, G_E), [12, n, n]."""
+    X, Y = grid2(n)
+    k = 2.0 * math.pi
+    sx, cx, sy, cy = np.sin(k * X), np.cos(k * X), np.sin(k * Y), np.cos(k * Y)
+    rho = 1.0 + 0.2 * sx * cy
+    rx, ry = 0.2 * k * cx * cy, -0.2 * k * sx * sy
+    u = np.full_like(rho, 3.0)
+    v = 2.0 + 0.15 * sx * sy
+    vx, vy = 0.15 * k * cx * sy, 0.15 * k * sx * cy
+    p = 1.0 / gamma + (rho - 1.0)
+    kin = 0.5 * (u * u + v * v)
+    E = p / (gamma - 1.0) + rho * kin
+    Ex = rx / (gamma - 1.0) + rx * kin + rho * v * vx
+    Ey = ry / (gamma - 1.0) + ry * kin + rho * v * vy
+    return np.stack([rho, rho * u, rho * v, E, rx, ry, rx * u, ry * u, rx * v + rho * vx, ry * v + rho * vy,
+                     Ex, Ey])
 
 
 def neohooke_initial(n: int, seeds=SEED_DISPLACEMENT):

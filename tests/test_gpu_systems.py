@@ -163,3 +163,24 @@ def test_nse_matches_oracle(lattice, shape, storage, tol):
     print("rel L2", {k: f"{v:.3e}" for k, v in errs.items()})
     for k, v in errs.items():
         assert v <= tol, k
+
+
+CNSF_MU = 3.52 / (1.225 * 340.2)
+CNSF_K = 4980.0 / (287.0 * 1.225 * 340.2)
+
+
+@pytest.mark.parametrize("lattice,shape,storage,tol", [
+    ("D2Q5", (64, 64), "f32", 1e-6), ("D2Q9", (40, 56), "f32", 1e-6), ("D2Q5", (64, 64), "f64", 1e-12)])
+def test_cnsf2d_matches_oracle(lattice, shape, storage, tol):
+    """The paper's 2D compressible NSF state at t = 0 (Mach 3 / 2 background,
+    exact conserved-field trackers; mu, K / R read with rho0 = cs = 1),
+    diffusive recipe f = 2, tau_R = 60, g_tau = 6, unforced."""
+    print(f"cnsf_trk2d {lattice} {storage} {shape} 500 steps", flush=True)
+    fQ, _ = mms.cnsf2d_paper(CNSF_MU, CNSF_K)
+    Qg, Qo = run_pair("cnsf_trk2d", lattice, shape, 2.0, 60.0, 500, storage,
+                      {"gamma": GAMMA, "mu": CNSF_MU, "kappa": CNSF_K, "R_gas": 1.0, "g_tau": 6.0}, fQ,
+                      diffusive=True)
+    errs = {"rho": rel(Qg[0], Qo[0]), "m": rel(Qg[1:3], Qo[1:3]), "E": rel(Qg[3], Qo[3]), "G": rel(Qg[4:], Qo[4:])}
+    print("rel L2", {k: f"{v:.3e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= tol, k
