@@ -26,7 +26,8 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E nameplate
-KERNEL_SOURCES = ["paper_2607_05668_amd/csrc/kernels.hip", "paper_2607_05668_amd/csrc/systems.hpp",
+KERNEL_SOURCES = ["paper_2607_05668_amd/csrc/step_kernels.hpp", "paper_2607_05668_amd/csrc/sys_swe.hip",
+                  "paper_2607_05668_amd/csrc/kernels.hip", "paper_2607_05668_amd/csrc/systems.hpp",
                   "paper_2607_05668_amd/csrc/lattices.hpp", "paper_2607_05668_amd/csrc/impl.hpp",
                   "paper_2607_05668_amd/csrc/dual.hpp", "paper_2607_05668_amd/csrc/device_common.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_swe1024.json")

@@ -29,23 +29,30 @@ def _run(cmd, verbose):
     subprocess.run(cmd, check=True)
 
 
-def build(verbose: bool = False, jobs: int = 2, out_dir: str = OUT_DIR, defines=()) -> str:
-    """Compile the library into out_dir; defines: extra -D tuning macros."""
+def build(verbose: bool = False, jobs: int = 0, out_dir: str = OUT_DIR, defines=()) -> str:
+    """Compile the library into out_dir, at most `jobs` translation units at
+    a time (0: up to 8, bounded by the CPU count); defines: extra -D tuning
+    macros."""
     os.makedirs(out_dir, exist_ok=True)
     lib = os.path.join(out_dir, "liblbm.so")
-    objs = []
-    procs = []
-    units = [("kernels.hip", True), ("kernels_ne.hip", True), ("lbm_api.cpp", True)]
+    jobs = jobs or max(1, min(8, os.cpu_count() or 1))
+    units = [(name, True) for name in sorted(os.listdir(SRC)) if name.endswith(".hip")] + [("lbm_api.cpp", True)]
+    cmds, objs = [], []
     for name, dev in units:
         obj = os.path.join(out_dir, os.path.splitext(name)[0] + ".o")
-        cmd = [HIPCC] + COMMON + ["-D" + d for d in defines] + (DEVICE if dev else []) + \
-            ["-c", os.path.join(SRC, name), "-o", obj]
+        cmds.append([HIPCC] + COMMON + ["-D" + d for d in defines] + (DEVICE if dev else []) +
+                    ["-c", os.path.join(SRC, name), "-o", obj])
+        objs.append(obj)
+    running, failed = [], False
+    for cmd in cmds:
         if verbose:
             print(" ".join(cmd), flush=True)
-        procs.append(subprocess.Popen(cmd))
-        objs.append(obj)
-    rc = [p.wait() for p in procs]
-    if any(rc):
+        running.append(subprocess.Popen(cmd))
+        while len(running) >= jobs:
+            failed |= running.pop(0).wait() != 0
+    for p in running:
+        failed |= p.wait() != 0
+    if failed:
         raise RuntimeError("hipcc failed")
     tmp = lib + ".tmp"
     _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs, verbose)

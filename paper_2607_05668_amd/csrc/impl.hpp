@@ -76,6 +76,18 @@ struct Launchers {
 };
 
 const Launchers *lbm_launchers(int sys, int lat, int storage);
+// per system family (sys_*.hip); nullptr for an unsupported lattice
+const Launchers *lbm_launchers_swe(int lat, int storage);
+const Launchers *lbm_launchers_advdiff(int lat, int storage);
+const Launchers *lbm_launchers_neohooke(int lat, int storage);
+const Launchers *lbm_launchers_nsf17(int lat, int storage);
+const Launchers *lbm_launchers_burgers(int lat, int storage);
+const Launchers *lbm_launchers_euler(int lat, int storage);
+const Launchers *lbm_launchers_maxwell(int lat, int storage);
+const Launchers *lbm_launchers_allencahn(int lat, int storage);
+const Launchers *lbm_launchers_relhydro(int lat, int storage);
+const Launchers *lbm_launchers_nse(int lat, int storage);
+const Launchers *lbm_launchers_cnsf2d(int lat, int storage);
 const Launchers *lbm_launchers_ne(int sys, int lat);   // storage LBM_F16NE
 hipError_t lbm_launch_copy(void *dst, const void *src, size_t n, hipStream_t s);
 hipError_t lbm_launch_streams(void *dst, const void *src, int nx, int ny, int fields, hipStream_t s);

@@ -1,0 +1,5 @@
+// Launchers of inviscid Burgers and compressible Euler (all storages, D2Q5 and D2Q9).
+#include "step_kernels.hpp"
+
+LBM_DEFINE_LAUNCHERS_2D(lbm_launchers_burgers, SysBurgers)
+LBM_DEFINE_LAUNCHERS_2D(lbm_launchers_euler, SysEuler)

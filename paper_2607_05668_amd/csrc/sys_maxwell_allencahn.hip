@@ -1,0 +1,5 @@
+// Launchers of Maxwell TM and Allen-Cahn (all storages, D2Q5 and D2Q9).
+#include "step_kernels.hpp"
+
+LBM_DEFINE_LAUNCHERS_2D(lbm_launchers_maxwell, SysMaxwell)
+LBM_DEFINE_LAUNCHERS_2D(lbm_launchers_allencahn, SysAllenCahn)

@@ -1,0 +1,5 @@
+// Launchers of the ultrarelativistic fluid and the weakly compressible NSE (all storages, D2Q5 and D2Q9).
+#include "step_kernels.hpp"
+
+LBM_DEFINE_LAUNCHERS_2D(lbm_launchers_relhydro, SysRelHydro)
+LBM_DEFINE_LAUNCHERS_2D(lbm_launchers_nse, SysNSE)
