@@ -29,18 +29,20 @@ from .build import LIB, build
 
 SYSTEMS = {"advdiff_trk2d": 0, "swe2d": 1, "neohooke2d": 2, "nsf3d_trk17": 3, "burgers2d": 4, "euler2d": 5,
            "maxwell2d": 6, "allencahn_trk2d": 7, "relhydro2d": 8, "nse_trk2d": 9,
-           "cnsf_trk2d": 10}
+           "cnsf_trk2d": 10, "mhd_trk2d": 11}
 LATTICES = {"D2Q5": 0, "D2Q9": 1, "D3Q7": 2}
 LATTICE_DIM = {"D2Q5": 2, "D2Q9": 2, "D3Q7": 3}
 SYSTEM_DIM = {"advdiff_trk2d": 2, "swe2d": 2, "neohooke2d": 2, "nsf3d_trk17": 3, "burgers2d": 2, "euler2d": 2,
               "maxwell2d": 2, "allencahn_trk2d": 2, "relhydro2d": 2, "nse_trk2d": 2,
-              "cnsf_trk2d": 2}
+              "cnsf_trk2d": 2, "mhd_trk2d": 2}
 PARAM_INDEX = {"g": 0, "ax": 1, "ay": 2, "az": 3, "nu": 4, "R": 5, "tau_grad": 6,
                "gamma": 7, "mu": 8, "kappa": 9, "rho0": 10, "mu_s": 11, "lambda_s": 12,
-               "c": 13, "cs_phys": 14, "R_gas": 15}
+               "c": 13, "cs_phys": 14, "R_gas": 15,
+               "eta": 4}
 TRACKER_FIELDS = {"advdiff_trk2d": range(1, 3), "nsf3d_trk17": range(5, 17), "allencahn_trk2d": range(1, 3),
-                  "nse_trk2d": range(3, 7), "cnsf_trk2d": range(4, 12)}
-MAXK = 17
+                  "nse_trk2d": range(3, 7), "cnsf_trk2d": range(4, 12),
+                  "mhd_trk2d": range(6, 18)}
+MAXK = 18
 
 
 class _Cfg(ctypes.Structure):

@@ -29,11 +29,12 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define MAXK 17
+#define MAXK 18
 #define MAXQ 9
 
 enum { SYS_ADVDIFF = 0, SYS_SWE = 1, SYS_NEOHOOKE = 2, SYS_NSF17 = 3, SYS_BURGERS = 4, SYS_EULER = 5,
-       SYS_MAXWELL = 6, SYS_ALLENCAHN = 7, SYS_RELHYDRO = 8, SYS_NSE = 9, SYS_CNSF2D = 10 };
+       SYS_MAXWELL = 6, SYS_ALLENCAHN = 7, SYS_RELHYDRO = 8, SYS_NSE = 9, SYS_CNSF2D = 10,
+       SYS_MHD = 11 };
 enum { LAT_D2Q5 = 0, LAT_D2Q9 = 1, LAT_D3Q7 = 2 };
 enum {
     P_G = 0, P_AX, P_AY, P_AZ, P_NU, P_R, P_TAUG, P_GAMMA, P_MU, P_KAPPA,
@@ -106,6 +107,7 @@ static int system_K(int sys)
     case SYS_RELHYDRO: return 3;
     case SYS_NSE: return 7;
     case SYS_CNSF2D: return 12;
+    case SYS_MHD: return 18;
     }
     return 0;
 }

@@ -27,6 +27,7 @@ Cases:
   nondimensional, trackers exact.
 * ``cnsf2d_paper`` -- the paper's 2D compressible NSF MMS (Mach 3 / 2),
   trackers exact.
+* ``mhd_paper``  -- the paper's resistive-MHD MMS, trackers exact.
 * ``nsf17``      -- the 3D compressible NSF manufactured solution with the
   shapes of the paper's homogenized-NSF MMS (porosity 1), conserved rows
   forced; tracker rows are forced only when ``force_trackers`` is set.
@@ -278,6 +279,66 @@ def cnsf2d_paper(mu, kappa, R=1.0, gamma=1.4, rho0=1.0, cs=1.0):
     Phi.append([(E + p) * u[c] - (tau[c][0] * u[0] + tau[c][1] * u[1]) - Kf * gT[c] for c in range(2)])
     res = [sp.diff(Qc[k], T) + _div(Phi[k], (X, Y)) for k in range(4)] + [sp.Integer(0)] * 8
     fQ = sp.lambdify((X, Y, T), Q, "numpy", cse=True)
+    fS = sp.lambdify((X, Y, T), res, "numpy", cse=True)
+    return _wrap2(fQ), _wrap2(fS)
+
+
+# ----------------------------------------------------------------- MHD ----
+def mhd_exact_exprs(rho0=1.0, cs=1.0, gamma=1.4):
+    """The paper's resistive-MHD MMS (supplement): per-axis Mach-3 flow, field
+    in Alfven units with background (0.5, 0.5) cs, fluctuations 0.3 rho0 and
+    0.3 cs in the printed modes (div dB = 0), dp = cs^2 drho + 0.2 p0 mode."""
+    r0, c, gm = sp.Float(rho0), sp.Float(cs), sp.Float(gamma)
+    p0 = r0 * c ** 2 / gm
+    k = PI2
+    drho = sp.Rational(3, 10) * r0 * sp.sin(k * X) * sp.cos(k * Y) * sp.cos(T)
+    dp = c ** 2 * drho + sp.Rational(1, 5) * p0 * sp.cos(k * X) * sp.sin(k * Y) * sp.sin(T)
+    u = 3 * c + sp.Rational(3, 10) * c * sp.cos(k * X) * sp.sin(k * Y) * sp.sin(T)
+    v = 3 * c + sp.Rational(3, 10) * c * sp.sin(k * X) * sp.sin(k * Y) * sp.sin(T)
+    Bx = c / 2 - sp.Rational(3, 10) * c * sp.cos(k * X) * sp.sin(k * Y) * sp.sin(T)
+    By = c / 2 + sp.Rational(3, 10) * c * sp.sin(k * X) * sp.cos(k * Y) * sp.sin(T)
+    rho = r0 + drho
+    p = p0 + dp
+    E = p / (gm - 1) + rho * (u ** 2 + v ** 2) / 2 + (Bx ** 2 + By ** 2) / 2
+    return [rho, rho * u, rho * v, E, Bx, By]
+
+
+@functools.lru_cache(maxsize=None)
+def mhd_paper(mu, kappa, eta, gamma=1.4, rho0=1.0, cs=1.0):
+    """(exact -> [18, ...], forcing -> [18, ...]): conserved rows forced with
+    the flux and the Powell source at the exact trackers, tracker rows not."""
+    Qc = mhd_exact_exprs(rho0, cs, gamma)
+    G = [sp.diff(Qc[f], v) for f in range(6) for v in (X, Y)]
+    gm, muf, Kf, ef = sp.Float(gamma), sp.Float(mu), sp.Float(kappa), sp.Float(eta)
+    rho, m0, m1, E, B0, B1 = Qc
+    m, B = [m0, m1], [B0, B1]
+    u = [m0 / rho, m1 / rho]
+    pg = (gm - 1) * (E - (m0 * u[0] + m1 * u[1]) / 2 - (B0 ** 2 + B1 ** 2) / 2)
+    ptot = pg + (B0 ** 2 + B1 ** 2) / 2
+    Gr, Gm, GE, GB = G[0:2], [G[2:4], G[4:6]], G[6:8], [G[8:10], G[10:12]]
+    du = [[(Gm[a][b] - u[a] * Gr[b]) / rho for b in range(2)] for a in range(2)]
+    div = du[0][0] + du[1][1]
+    tau = [[muf * (du[a][b] + du[b][a] - (sp.Rational(2, 3) * div if a == b else 0)) for b in range(2)]
+           for a in range(2)]
+    gT = []
+    for b in range(2):
+        gp = (gm - 1) * (GE[b] - (u[0] * Gm[0][b] + u[1] * Gm[1][b]) + (u[0] ** 2 + u[1] ** 2) * Gr[b] / 2
+                         - (B0 * GB[0][b] + B1 * GB[1][b]))
+        gT.append((gp - pg * Gr[b] / rho) / rho)
+    j = GB[1][0] - GB[0][1]
+    uB = u[0] * B0 + u[1] * B1
+    jxB = [-j * B1, j * B0]
+    divB = GB[0][0] + GB[1][1]
+    Phi = [[m0, m1]]
+    for a in range(2):
+        Phi.append([m[a] * u[c] + (ptot if a == c else 0) - B[a] * B[c] - tau[a][c] for c in range(2)])
+    Phi.append([(E + ptot) * u[c] - B[c] * uB - (tau[c][0] * u[0] + tau[c][1] * u[1]) - Kf * gT[c] + ef * jxB[c]
+                for c in range(2)])
+    for a in range(2):
+        Phi.append([B[a] * u[c] - u[a] * B[c] - ef * GB[a][c] for c in range(2)])
+    S = [0, -divB * B0, -divB * B1, -divB * uB, -divB * u[0], -divB * u[1]]
+    res = [sp.diff(Qc[k], T) + _div(Phi[k], (X, Y)) - S[k] for k in range(6)] + [sp.Integer(0)] * 12
+    fQ = sp.lambdify((X, Y, T), Qc + G, "numpy", cse=True)
     fS = sp.lambdify((X, Y, T), res, "numpy", cse=True)
     return _wrap2(fQ), _wrap2(fS)
 

@@ -1154,3 +1154,140 @@ def test_cnsf2d_mms_near_second_order():
     a, b = _cnsf2d_errors(64), _cnsf2d_errors(128)
     for k in ("rho", "m", "E"):
         assert 1.65 < math.log2(a[k] / b[k]) < 2.2, k
+
+
+# ---------------------------------------------------------------- MHD ----
+def test_mhd_flux_source_match_printed_expansion():
+    """Supplement, resistive MHD: the compiler-expanded momentum, energy and
+    induction fluxes, tracker rows and Powell sources at random states
+    (gamma = 1.4, mu = 0.013, K = 0.017, eta = 0.021).  Printed state order
+    (Q6 = G_rho,0, Q8 = G_(rho u),1,0, Q10 = G_E,0, Q12 = G_B,1,0,
+    Q14 = G_(rho u),0,0, Q16 = G_B,0,0) mapped to this oracle's."""
+    g, mu, K, eta = 1.4, 0.013, 0.017, 0.021
+    o = _mk("mhd_trk2d", "D2Q5", {"gamma": g, "mu": mu, "kappa": K, "eta": eta},
+            [1, 3, 3, 12, 0.5, 0.5] + [0] * 12, 4.0, 4, lam=0.02)
+    tg = o.params["tau_grad"]
+    rng = np.random.default_rng(71)
+    for _ in range(20):
+        r = rng.uniform(0.8, 1.2)
+        m0, m1 = rng.uniform(-3, 3, 2)
+        E = rng.uniform(10, 14)
+        B0, B1 = rng.uniform(-1, 1, 2)
+        Gr0, Gr1, Gm00, Gm01, Gm10, Gm11, GE0, GE1, GB00, GB01, GB10, GB11 = rng.uniform(-1, 1, 12)
+        q = [r, m0, m1, E, B0, B1, Gr0, Gr1, Gm00, Gm01, Gm10, Gm11, GE0, GE1, GB00, GB01, GB10, GB11]
+        F, S = o.flux(q), o.source(q)
+        P10 = (-B0 ** 2 * g / 2 - B1 ** 2 * g / 2 + B1 ** 2 + E * g - E + 4 * Gr0 * mu * m0 / (3 * r * r)
+               - 2 * Gr1 * mu * m1 / (3 * r * r) - 4 * Gm00 * mu / (3 * r) + 2 * Gm11 * mu / (3 * r)
+               - g * m0 ** 2 / (2 * r) - g * m1 ** 2 / (2 * r) + 3 * m0 ** 2 / (2 * r) + m1 ** 2 / (2 * r))
+        P11 = (-B0 * B1 + Gr0 * mu * m1 / r ** 2 + Gr1 * mu * m0 / r ** 2 - Gm01 * mu / r - Gm10 * mu / r
+               + m0 * m1 / r)
+        P21 = (-B0 ** 2 * g / 2 + B0 ** 2 - B1 ** 2 * g / 2 + E * g - E - 2 * Gr0 * mu * m0 / (3 * r * r)
+               + 4 * Gr1 * mu * m1 / (3 * r * r) + 2 * Gm00 * mu / (3 * r) - 4 * Gm11 * mu / (3 * r)
+               - g * m0 ** 2 / (2 * r) - g * m1 ** 2 / (2 * r) + m0 ** 2 / (2 * r) + 3 * m1 ** 2 / (2 * r))
+        P30 = (-B0 ** 2 * Gr0 * K * g / (2 * r * r) + B0 ** 2 * Gr0 * K / (2 * r * r) - B0 ** 2 * g * m0 / (2 * r)
+               - B0 * B1 * m1 / r + B0 * GB00 * K * g / r - B0 * GB00 * K / r - B1 ** 2 * Gr0 * K * g / (2 * r * r)
+               + B1 ** 2 * Gr0 * K / (2 * r * r) - B1 ** 2 * g * m0 / (2 * r) + B1 ** 2 * m0 / r + B1 * GB01 * eta
+               + B1 * GB10 * K * g / r - B1 * GB10 * K / r - B1 * GB10 * eta + E * Gr0 * K * g / r ** 2
+               - E * Gr0 * K / r ** 2 + E * g * m0 / r - GE0 * K * g / r + GE0 * K / r
+               - Gr0 * K * g * m0 ** 2 / r ** 3 - Gr0 * K * g * m1 ** 2 / r ** 3 + Gr0 * K * m0 ** 2 / r ** 3
+               + Gr0 * K * m1 ** 2 / r ** 3 + 4 * Gr0 * mu * m0 ** 2 / (3 * r ** 3) + Gr0 * mu * m1 ** 2 / r ** 3
+               + Gr1 * mu * m0 * m1 / (3 * r ** 3) + Gm00 * K * g * m0 / r ** 2 - Gm00 * K * m0 / r ** 2
+               - 4 * Gm00 * mu * m0 / (3 * r ** 2) - Gm01 * mu * m1 / r ** 2 + Gm10 * K * g * m1 / r ** 2
+               - Gm10 * K * m1 / r ** 2 - Gm10 * mu * m1 / r ** 2 + 2 * Gm11 * mu * m0 / (3 * r ** 2)
+               - g * m0 ** 3 / (2 * r * r) - g * m0 * m1 ** 2 / (2 * r * r) + m0 ** 3 / (2 * r * r)
+               + m0 * m1 ** 2 / (2 * r * r))
+        P31 = (-B0 ** 2 * Gr1 * K * g / (2 * r * r) + B0 ** 2 * Gr1 * K / (2 * r * r) - B0 ** 2 * g * m1 / (2 * r)
+               + B0 ** 2 * m1 / r - B0 * B1 * m0 / r + B0 * GB01 * K * g / r - B0 * GB01 * K / r - B0 * GB01 * eta
+               + B0 * GB10 * eta - B1 ** 2 * Gr1 * K * g / (2 * r * r) + B1 ** 2 * Gr1 * K / (2 * r * r)
+               - B1 ** 2 * g * m1 / (2 * r) + B1 * GB11 * K * g / r - B1 * GB11 * K / r + E * Gr1 * K * g / r ** 2
+               - E * Gr1 * K / r ** 2 + E * g * m1 / r - GE1 * K * g / r + GE1 * K / r
+               + Gr0 * mu * m0 * m1 / (3 * r ** 3) - Gr1 * K * g * m0 ** 2 / r ** 3 - Gr1 * K * g * m1 ** 2 / r ** 3
+               + Gr1 * K * m0 ** 2 / r ** 3 + Gr1 * K * m1 ** 2 / r ** 3 + Gr1 * mu * m0 ** 2 / r ** 3
+               + 4 * Gr1 * mu * m1 ** 2 / (3 * r ** 3) + 2 * Gm00 * mu * m1 / (3 * r ** 2)
+               + Gm01 * K * g * m0 / r ** 2 - Gm01 * K * m0 / r ** 2 - Gm01 * mu * m0 / r ** 2
+               - Gm10 * mu * m0 / r ** 2 + Gm11 * K * g * m1 / r ** 2 - Gm11 * K * m1 / r ** 2
+               - 4 * Gm11 * mu * m1 / (3 * r ** 2) - g * m0 ** 2 * m1 / (2 * r * r) - g * m1 ** 3 / (2 * r * r)
+               + m0 ** 2 * m1 / (2 * r * r) + m1 ** 3 / (2 * r * r))
+        printed = {(0, 0): m0, (0, 1): m1, (1, 0): P10, (1, 1): P11, (2, 0): P11, (2, 1): P21,
+                   (3, 0): P30, (3, 1): P31,
+                   (4, 0): -GB00 * eta, (4, 1): B0 * m1 / r - B1 * m0 / r - GB01 * eta,
+                   (5, 0): -B0 * m1 / r + B1 * m0 / r - GB10 * eta, (5, 1): -GB11 * eta}
+        for (k, c), v in printed.items():
+            assert F[k, c] == pytest.approx(v, rel=1e-12, abs=1e-12), (k, c)
+        x = (r, m0, m1, E, B0, B1)
+        for f in range(6):
+            for b in range(2):
+                for c in range(2):
+                    want = q[6 + 2 * f + b] * (m0, m1)[c] / r - (x[f] / tg if b == c else 0.0)
+                    assert F[6 + 2 * f + b, c] == pytest.approx(want, rel=1e-12, abs=1e-12)
+        Sp = [0.0, -B0 * GB00 - B0 * GB11, -B1 * GB00 - B1 * GB11,
+              -B0 * GB00 * m0 / r - B0 * GB11 * m0 / r - B1 * GB00 * m1 / r - B1 * GB11 * m1 / r,
+              -GB00 * m0 / r - GB11 * m0 / r, -GB00 * m1 / r - GB11 * m1 / r]
+        assert np.allclose(S[:6], Sp, rtol=1e-13, atol=1e-15)
+        assert np.allclose(S[6:], -np.array(q[6:]) / tg, rtol=1e-14, atol=0)
+
+
+def test_mhd_mms_fields_match_printed_expansion():
+    """Supplement, MHD MMS: printed expanded conserved fields and magnetic
+    field in rho0, cs (SI 1.225, 340)."""
+    r0, c = 1.225, 340.0
+    f = sp.lambdify((mms.X, mms.Y, mms.T), mms.mhd_exact_exprs(r0, c, 1.4), "numpy")
+    rng = np.random.default_rng(72)
+    for x, y, t in rng.uniform(0, 1, (10, 3)):
+        sx, cx = math.sin(2 * math.pi * x), math.cos(2 * math.pi * x)
+        sy, cy = math.sin(2 * math.pi * y), math.cos(2 * math.pi * y)
+        st, ct = math.sin(t), math.cos(t)
+        rho = 3 * r0 * sx * ct * cy / 10 + r0
+        a = 3 * c * st * sy * cx / 10 + 3 * c
+        b = 3 * c * st * sx * sy / 10 + 3 * c
+        q3 = (5 * c * c * r0 * st * sy * cx / 14 + 3 * c * c * r0 * sx * ct * cy / 4 + 25 * c * c * r0 / 14
+              + (3 * c * st * sx * cy / 10 + c / 2) ** 2 / 2 + (-3 * c * st * sy * cx / 10 + c / 2) ** 2 / 2
+              + (3 * r0 * sx * ct * cy / 20 + r0 / 2) * (b * b + a * a))
+        printed = [rho, a * rho, b * rho, q3, -3 * c * st * sy * cx / 10 + c / 2, 3 * c * st * sx * cy / 10 + c / 2]
+        assert np.allclose(np.array(f(x, y, t), dtype=float), printed, rtol=1e-12, atol=0)
+
+
+def _mhd_errors(n):
+    g = _gold("mms_printed.json")
+    rec, si = g["recipes"]["mhd_double"], g["mhd_mms_SI"]
+    # nondimensional reading (rho0 = cs = L = 1): mu, K / (rho0 cs L), eta / (cs L)
+    mu = si["mu"] / (si["rho0"] * si["cs"])
+    K = si["K"] / (si["rho0"] * si["cs"])
+    eta = si["eta"] / si["cs"]
+    gm = si["gamma"]
+    fQ, fS = mms.mhd_paper(mu, K, eta, gamma=gm)
+    dx, dt, tau = oracle.recipe(n, "acoustic", rec["f"], rec["tau_r"])
+    X, Y = inputs.grid2(n)
+    o = oracle.Oracle("mhd_trk2d", "D2Q5", (n, n), dt, dx, tau, rec["g_tau"],
+                      {"gamma": gm, "mu": mu, "kappa": K, "eta": eta},
+                      Q0=[1.0, 3.0, 3.0, 1 / gm / (gm - 1) + 9.25, 0.5, 0.5] + [0.0] * 12)
+    o.init(fQ(X, Y, 0.0))
+    o.step(int(round(1.0 / dt)), source=lambda t: fS(X, Y, t))
+    Qn, Qe = o.moments(), fQ(X, Y, o.t)
+    return {"rho": mms.rel_l2(Qn[0], Qe[0]), "E": mms.rel_l2(Qn[3], Qe[3]),
+            "m": math.hypot(mms.rel_l2(Qn[1], Qe[1]), mms.rel_l2(Qn[2], Qe[2])),
+            "B": math.hypot(mms.rel_l2(Qn[4], Qe[4]), mms.rel_l2(Qn[5], Qe[5]))}
+
+
+def test_mhd_mms_magnitude_at_64():
+    """Resistive MHD MMS (Mach 3 per axis, plasma beta 4 / gamma, read with
+    rho0 = cs = 1: mu = K = eta = 0.01) under the acoustic recipe f = 0.025,
+    tau_R = 140, g_tau = 4.  The N = 64 errors of B, E, rho and rho u sit
+    2^(3 x printed LSQ order +- 0.2) above the printed N = 512 errors
+    (oracle: 2^6.59, 2^5.89, 2^5.10, 2^5.64)."""
+    g = _gold("mms_printed.json")
+    e = _mhd_errors(64)
+    for k in ("B", "E", "rho", "m"):
+        s = g[f"mhd_double_{k}_eoc_L2"]
+        assert 2 ** (3 * s - 0.2) < e[k] / g[f"mhd_double_{k}_relL2_N512"] < 2 ** (3 * s + 0.2), k
+
+
+@pytest.mark.slow
+def test_mhd_mms_at_128():
+    """N = 128 errors sit 2^(2 x printed order +- 0.3) above the printed
+    N = 512 errors (oracle: 2^4.17, 2^3.98, 2^3.66, 2^3.84)."""
+    g = _gold("mms_printed.json")
+    e = _mhd_errors(128)
+    for k in ("B", "E", "rho", "m"):
+        s = g[f"mhd_double_{k}_eoc_L2"]
+        assert 2 ** (2 * s - 0.3) < e[k] / g[f"mhd_double_{k}_relL2_N512"] < 2 ** (2 * s + 0.3), k
