@@ -198,6 +198,8 @@ def extra_runs(torch, lbm, inputs):
     one("nse_trk2d_D2Q5_f32_2048", p, 2048, "f32", 200, 280, inputs.nse_initial(2048))
     p = inputs.PRESETS["cnsf2048"]
     one("cnsf_trk2d_D2Q5_f32_2048", p, 2048, "f32", 100, 480, inputs.cnsf2d_initial(2048))
+    p = inputs.PRESETS["mhd2048"]
+    one("mhd_trk2d_D2Q5_f32_2048", p, 2048, "f32", 100, 720, inputs.mhd_initial(2048))
     p = inputs.PRESETS["advdiff64"]
     one("advdiff_D2Q5_f64_64", p, 64, "f64", 200, 240, inputs.advdiff_initial(64))
     p = inputs.PRESETS["nsf256"]

@@ -82,6 +82,17 @@ enum {                      /* lbm_reduce: what                                 
  *            "maxwell2d"     Maxwell, transverse-magnetic mode (E_z, H_x, H_y), Sec. 3
  *            "allencahn_trk2d" Allen-Cahn phase field with a gradient
  *                            tracker (phi, G_phi), Sec. 3
+ *            "relhydro2d"    ideal ultrarelativistic fluid (E, S0, S1), c = 1, Sec. 3
+ *            "nse_trk2d"     weakly compressible Navier-Stokes (rho, rho u0,
+ *                            rho u1) with momentum-gradient trackers, Sec. 3
+ *            "cnsf_trk2d"    2D compressible Navier-Stokes-Fourier (rho,
+ *                            rho u0, rho u1, E) with conserved-field gradient
+ *                            trackers (12 fields), Sec. 3
+ *            "mhd_trk2d"     2D resistive MHD (rho, rho u0, rho u1, E, B0, B1;
+ *                            B in Alfven units) with conserved-field gradient
+ *                            trackers and the Powell source (18 fields), Sec. 3
+ *   Tracker layout (2D): tracker fields follow the conserved fields, two
+ *   per tracked field in field order (G_q,0, G_q,1).
  *   lattice: "D2Q5" | "D2Q9" (2D systems) | "D3Q7" (3D systems)
  *   nx, ny, nz: grid; nz must be 1 in 2D (rows whose length is a multiple
  *   of 64 map onto whole wavefronts; any size is accepted).
@@ -109,6 +120,12 @@ int lbm_num_velocities(const lbm_state *h);
  *   euler2d:        gamma (adiabatic index, default 1.4)
  *   maxwell2d:      c (wave speed, default 1)
  *   allencahn_trk2d: nu (interface diffusivity gamma), R (reaction rate r), g_tau
+ *   relhydro2d:     (none)
+ *   nse_trk2d:      cs_phys (physical sound speed), mu (dynamic viscosity), g_tau
+ *   cnsf_trk2d:     gamma, mu (dynamic viscosity), kappa (heat conductivity K),
+ *                   R_gas (T = p / (rho R_gas)), g_tau
+ *   mhd_trk2d:      gamma, mu (dynamic viscosity), kappa (heat-flux coefficient
+ *                   K, with T = p / rho), eta (magnetic diffusivity), g_tau
  *   all:            t0 (initial time) */
 int lbm_set_param(lbm_state *h, const char *name, double v);
 
@@ -132,7 +149,10 @@ int lbm_set_storage(lbm_state *h, int storage);
  * neohooke2d (1,0,0,1,0,0); nsf3d_trk17 (1, u0,u0,u0, E0, 0...) from the
  * mms_* parameters; euler2d (1, 3, 3, 1/(gamma (gamma-1)) + 9), the
  * Mach-3 background of the paper's manufactured solution in units
- * rho0 = cs = 1; burgers2d, maxwell2d, allencahn_trk2d all zeros. */
+ * rho0 = cs = 1; cnsf_trk2d (1, 3, 2, 1/(gamma (gamma-1)) + 13/2, 0...);
+ * mhd_trk2d (1, 3, 3, 1/(gamma (gamma-1)) + 37/4, 1/2, 1/2, 0...);
+ * relhydro2d (3, 1.2, 1.2); nse_trk2d (1, 0...); burgers2d, maxwell2d,
+ * allencahn_trk2d all zeros. */
 int lbm_set_reference(lbm_state *h, const double *Q0);
 int lbm_get_reference(const lbm_state *h, double *Q0_out);
 

@@ -96,6 +96,7 @@ KParams<R> lbm_state_impl::kparams(double t_half) const
         if (sys == SYS_ALLENCAHN) trk = SysAllenCahn::tracker(k);
         if (sys == SYS_NSE) trk = SysNSE::tracker(k);
         if (sys == SYS_CNSF2D) trk = SysCNSF2D::tracker(k);
+        if (sys == SYS_MHD) trk = SysMHD::tracker(k);
         const double om = trk ? omega_t : omega_c;
         p.omega[k] = (R)om;
         p.delta[k] = (R)(2.0 - om);
@@ -147,6 +148,12 @@ KParams<R> lbm_state_impl::kparams(double t_half) const
         d.mm0_h0[0] = Q0[1] * Q0[1] / d.H_ref;
         d.mm0_h0[1] = Q0[1] * Q0[2] / d.H_ref;
         d.mm0_h0[2] = Q0[2] * Q0[2] / d.H_ref;
+    }
+    if (sys == SYS_MHD) {
+        const double b2 = Q0[4] * Q0[4] + Q0[5] * Q0[5];
+        d.p_ref = (gamma - 1.0) * (Q0[3] - 0.5 * (Q0[1] * Q0[1] + Q0[2] * Q0[2]) / Q0[0] - 0.5 * b2);
+        d.H_ref = Q0[3] + d.p_ref + 0.5 * b2;        // E0 + p_tot0
+        for (int a = 0; a < 2; ++a) d.u_ref[a] = Q0[1 + a] / Q0[0];
     }
     d.cs2_phys = cs_phys * cs_phys;
     d.inv_R_gas = 1.0 / R_gas;
@@ -224,6 +231,7 @@ const Launchers *lbm_launchers(int sys, int lat, int storage)
     case SYS_RELHYDRO: return lbm_launchers_relhydro(lat, storage);
     case SYS_NSE: return lbm_launchers_nse(lat, storage);
     case SYS_CNSF2D: return lbm_launchers_cnsf2d(lat, storage);
+    case SYS_MHD: return lbm_launchers_mhd(lat, storage);
     }
     return nullptr;
 }

@@ -44,6 +44,7 @@ int system_id(const char *s)
     if (!std::strcmp(s, "relhydro2d")) return SYS_RELHYDRO;
     if (!std::strcmp(s, "nse_trk2d")) return SYS_NSE;
     if (!std::strcmp(s, "cnsf_trk2d")) return SYS_CNSF2D;
+    if (!std::strcmp(s, "mhd_trk2d")) return SYS_MHD;
     return -1;
 }
 
@@ -56,8 +57,8 @@ int lattice_id(const char *s)
     return -1;
 }
 
-const int kSysK[11] = {3, 3, 6, 17, 1, 4, 3, 3, 3, 7, 12};
-const int kSysD[11] = {2, 2, 2, 3, 2, 2, 2, 2, 2, 2, 2};
+const int kSysK[12] = {3, 3, 6, 17, 1, 4, 3, 3, 3, 7, 12, 18};
+const int kSysD[12] = {2, 2, 2, 3, 2, 2, 2, 2, 2, 2, 2, 2};
 const int kLatQ[3] = {5, 9, 7};
 const int kLatD[3] = {2, 2, 3};
 const double kLatCs2[3] = {1.0 / 3.0, 1.0 / 3.0, 1.0 / 4.0};
@@ -97,6 +98,20 @@ void cnsf2d_default_reference(lbm_state *h)
     h->Q0[3] = (1.0 / h->gamma) / (h->gamma - 1.0) + 6.5;
 }
 
+// Reference state of the 2D resistive MHD system: the background of the
+// paper's manufactured solution in units rho0 = cs = 1 (Mach 3 per axis,
+// field (1/2, 1/2) in Alfven units): E0 = p0 / (gamma - 1) + 9 + 1/4.
+void mhd_default_reference(lbm_state *h)
+{
+    std::memset(h->Q0, 0, sizeof h->Q0);
+    h->Q0[0] = 1.0;
+    h->Q0[1] = 3.0;
+    h->Q0[2] = 3.0;
+    h->Q0[3] = (1.0 / h->gamma) / (h->gamma - 1.0) + 9.25;
+    h->Q0[4] = 0.5;
+    h->Q0[5] = 0.5;
+}
+
 void default_reference(lbm_state *h)
 {
     std::memset(h->Q0, 0, sizeof h->Q0);
@@ -109,13 +124,15 @@ void default_reference(lbm_state *h)
     case SYS_RELHYDRO: h->Q0[0] = 3.0; h->Q0[1] = 1.2; h->Q0[2] = 1.2; break;
     case SYS_NSE: h->Q0[0] = 1.0; break;
     case SYS_CNSF2D: cnsf2d_default_reference(h); break;
+    case SYS_MHD: mhd_default_reference(h); break;
     case SYS_EULER: euler_default_reference(h); break;
     }
 }
 
 bool has_trackers(int sys)
 {
-    return sys == SYS_ADVDIFF || sys == SYS_NSF17 || sys == SYS_ALLENCAHN || sys == SYS_NSE || sys == SYS_CNSF2D;
+    return sys == SYS_ADVDIFF || sys == SYS_NSF17 || sys == SYS_ALLENCAHN || sys == SYS_NSE || sys == SYS_CNSF2D ||
+           sys == SYS_MHD;
 }
 
 size_t arith_bytes(const lbm_state *h) { return h->storage == LBM_F64 ? 8 : 4; }
@@ -241,6 +258,22 @@ int lbm_set_param(lbm_state *h, const char *name, double v)
         }
         break;
     case SYS_RELHYDRO:
+        break;
+    case SYS_MHD:
+        if (n == "gamma") {
+            if (!(v > 1)) return fail(h, LBM_EINVAL, "gamma must exceed 1");
+            h->gamma = v;
+            if (!h->q0_set) mhd_default_reference(h);
+            return LBM_OK;
+        }
+        if (n == "mu") { h->mu = v; return LBM_OK; }
+        if (n == "kappa") { h->kappa = v; return LBM_OK; }
+        if (n == "eta") { h->nu = v; return LBM_OK; }
+        if (n == "g_tau") {
+            if (!(v > 0)) return fail(h, LBM_EINVAL, "g_tau must be positive");
+            h->g_tau = v;
+            return LBM_OK;
+        }
         break;
     case SYS_CNSF2D:
         if (n == "gamma") {
@@ -586,7 +619,7 @@ int lbm_save(lbm_state *h, void *host_buf, size_t *n_inout)
     SaveHeader hd;
     std::memset(&hd, 0, sizeof hd);
     std::memcpy(hd.magic, "LBMCKPT1", 8);
-    hd.version = 1;
+    hd.version = 2;                       // 2: per-field header arrays of 18 entries
     hd.sys = h->sys;
     hd.lat = h->lat;
     hd.storage = h->storage;
@@ -620,7 +653,7 @@ int lbm_load(lbm_state *h, const void *host_buf, size_t n)
     if (!host_buf || n < sizeof(SaveHeader)) return fail(h, LBM_EINVAL, "checkpoint buffer too small");
     SaveHeader hd;
     std::memcpy(&hd, host_buf, sizeof hd);
-    if (std::memcmp(hd.magic, "LBMCKPT1", 8) != 0 || hd.version != 1) return fail(h, LBM_EINVAL, "not a checkpoint");
+    if (std::memcmp(hd.magic, "LBMCKPT1", 8) != 0 || hd.version != 2) return fail(h, LBM_EINVAL, "not a checkpoint of this version");
     if (hd.sys != h->sys || hd.lat != h->lat || hd.storage != h->storage || hd.nx != h->nx || hd.ny != h->ny ||
         hd.nz != h->nz)
         return fail(h, LBM_EINVAL, "checkpoint does not match this handle");

@@ -14,7 +14,7 @@
 
 #include "dual.hpp"
 
-#define LBM_MAXK 17
+#define LBM_MAXK 18
 
 // Per-run constants shared by all systems (filled on the host in double and
 // converted to the arithmetic type R).
@@ -469,6 +469,139 @@ struct SysCNSF2D {
         const R pr = (p.gamma - R(1)) * (Q[3] - R(0.5) * rho * (u0 * u0 + u1 * u1));
         const R c2 = p.gamma * pr / rho;
         return sqrt(u0 * u0 + u1 * u1) + sqrt(c2 > R(0) ? c2 : R(0));
+    }
+};
+
+// ----------------------------------------------------------------- MHD --
+// 2D resistive compressible MHD with Powell divergence cleaning and
+// conserved-field gradient trackers (Sec. 3): Q = (rho, m0, m1, E, B0, B1,
+// then the tracker pairs G_x,b ~ d_b x of x = rho, m0, m1, E, B0, B1),
+// p_gas = (gamma - 1)(E - |m|^2 / 2 rho - |B|^2 / 2), p_tot = p_gas + |B|^2 / 2,
+// T = p_gas / rho, Phi_m = m (x) u + p_tot I - B (x) B - tau,
+// Phi_E = (E + p_tot) u - B (u . B) - tau . u - K grad T + eta j x B,
+// Phi_B = B (x) u - u (x) B - eta G_B, Powell sources -div B (B, u . B, u)
+// with div B = tr G_B, gamma, mu, K = kappa, eta = nu.  Fluctuation form as
+// for the 2D compressible NSF; the dissipative and Lorentz-resistive terms
+// (small where the trackers are small) as value minus reference value.
+struct SysMHD {
+    static constexpr int K = 18, D = 2, id = 11;
+    static constexpr bool precise = false;   // plain exact-moment equilibrium (VALU budget)
+    static constexpr bool compensated = true;   // two-sum moments dQ = hi + lo
+    static constexpr bool tracker(int k) { return k >= 6; }
+
+    // tau, grad T and eta j x B of an absolute state
+    template <class S, class R>
+    __host__ __device__ static void diffusive(const Phys<R> &p, const S &rho, const S *u, const S &pg, const S *Q,
+                                              S tau[2][2], S *gT, S *jxB)
+    {
+        S du[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) du[a][b] = (Q[8 + 2 * a + b] - u[a] * Q[6 + b]) / rho;
+        const S div = du[0][0] + du[1][1];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                tau[a][b] = (a == b) ? (du[a][b] + du[b][a] - div * R(2.0 / 3.0)) * p.mu
+                                     : (du[a][b] + du[b][a]) * p.mu;
+        const S ku = (u[0] * u[0] + u[1] * u[1]) * R(0.5);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const S gp = (Q[12 + b] - (u[0] * Q[8 + b] + u[1] * Q[10 + b]) + ku * Q[6 + b]
+                          - (Q[4] * Q[14 + b] + Q[5] * Q[16 + b])) * (p.gamma - R(1));
+            gT[b] = (gp - pg * Q[6 + b] / rho) / rho;
+        }
+        const S j = (Q[16] - Q[15]) * p.nu;             // eta (d0 B1 - d1 B0)
+        jxB[0] = -j * Q[5];
+        jxB[1] = j * Q[4];
+    }
+
+    template <class S, class R>
+    __host__ __device__ static void flux_delta(const Phys<R> &p, const S *dQ, S dPhi[][D])
+    {
+        const S drho = dQ[0];
+        const S rho = drho + p.Q0[0];
+        const S irho = R(1) / rho;
+        S u[2], du[2], B[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            du[a] = (dQ[1 + a] - drho * p.u_ref[a]) * irho;
+            u[a] = du[a] + p.u_ref[a];
+            B[a] = dQ[4 + a] + p.Q0[4 + a];
+        }
+        const S dk = (rho * (du[0] * (du[0] + R(2) * p.u_ref[0]) + du[1] * (du[1] + R(2) * p.u_ref[1]))
+                      + drho * (p.u_ref[0] * p.u_ref[0] + p.u_ref[1] * p.u_ref[1])) * R(0.5);
+        const S dmag = dQ[4] * (dQ[4] * R(0.5) + p.Q0[4]) + dQ[5] * (dQ[5] * R(0.5) + p.Q0[5]);
+        const S dpg = (dQ[3] - dk - dmag) * (p.gamma - R(1));
+        const S dpt = dpg + dmag;
+        S Qa[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) Qa[k] = dQ[k] + p.Q0[k];
+        S tau[2][2], gT[2], jxB[2];
+        diffusive<S, R>(p, rho, u, dpg + p.p_ref, Qa, tau, gT, jxB);
+        R tau0[2][2], gT0[2], jxB0[2];
+        const R u0[2] = {p.u_ref[0], p.u_ref[1]};
+        diffusive<R, R>(p, p.Q0[0], u0, p.p_ref, p.Q0, tau0, gT0, jxB0);
+        const S dH = dQ[3] + dpt;                         // d(E + p_tot)
+        const R w0 = u0[0] * p.Q0[4] + u0[1] * p.Q0[5];   // u0 . B0
+        const S dw = du[0] * B[0] + du[1] * B[1] + u0[0] * dQ[4] + u0[1] * dQ[5];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            dPhi[0][c] = dQ[1 + c];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                S v = dQ[1 + a] * u[c] + du[c] * p.Q0[1 + a] - (dQ[4 + a] * B[c] + dQ[4 + c] * p.Q0[4 + a])
+                      - (tau[a][c] - tau0[a][c]);
+                if (a == c) v = v + dpt;
+                dPhi[1 + a][c] = v;
+            }
+            const S tu = (tau[c][0] - tau0[c][0]) * u[0] + (tau[c][1] - tau0[c][1]) * u[1]
+                         + du[0] * tau0[c][0] + du[1] * tau0[c][1];
+            dPhi[3][c] = dH * u[c] + du[c] * p.H_ref - (dQ[4 + c] * (dw + w0) + dw * p.Q0[4 + c]) - tu
+                         - (gT[c] - gT0[c]) * p.kappa + (jxB[c] - jxB0[c]);
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+                dPhi[4 + a][c] = (dQ[4 + a] * u[c] + du[c] * p.Q0[4 + a]) - (du[a] * B[c] + dQ[4 + c] * u0[a])
+                                 - dQ[14 + 2 * a + c] * p.nu;
+#pragma unroll
+            for (int f = 0; f < 6; ++f)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const int k = 6 + 2 * f + b;
+                    S v = dQ[k] * u[c] + du[c] * p.Q0[k];
+                    if (b == c) v = v - dQ[f] * p.inv_tau_grad;
+                    dPhi[k][c] = v;
+                }
+        }
+    }
+
+    template <class S, class R>
+    __host__ __device__ static void source(const Phys<R> &p, const S *dQ, const R *, S *Sk)
+    {
+        const S rho = dQ[0] + p.Q0[0];
+        const S u0 = (dQ[1] + p.Q0[1]) / rho, u1 = (dQ[2] + p.Q0[2]) / rho;
+        const S B0 = dQ[4] + p.Q0[4], B1 = dQ[5] + p.Q0[5];
+        const S divB = (dQ[14] + p.Q0[14]) + (dQ[17] + p.Q0[17]);
+        Sk[0] = S(R(0));
+        Sk[1] = -divB * B0;
+        Sk[2] = -divB * B1;
+        Sk[3] = -divB * (u0 * B0 + u1 * B1);
+        Sk[4] = -divB * u0;
+        Sk[5] = -divB * u1;
+#pragma unroll
+        for (int k = 6; k < K; ++k) Sk[k] = (dQ[k] + p.Q0[k]) * (-p.inv_tau_grad);
+    }
+
+    // |u| + sqrt(c^2 + |B|^2 / rho), a bound of the fast magnetosonic speed
+    template <class R>
+    __host__ __device__ static R max_speed(const Phys<R> &p, const R *Q)
+    {
+        const R rho = Q[0], u0 = Q[1] / rho, u1 = Q[2] / rho, b2 = Q[4] * Q[4] + Q[5] * Q[5];
+        const R pg = (p.gamma - R(1)) * (Q[3] - R(0.5) * rho * (u0 * u0 + u1 * u1) - R(0.5) * b2);
+        const R c2 = p.gamma * (pg > R(0) ? pg : R(0)) / rho + b2 / rho;
+        return sqrt(u0 * u0 + u1 * u1) + sqrt(c2);
     }
 };
 

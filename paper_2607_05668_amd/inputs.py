@@ -149,6 +149,10 @@ PRESETS = {
                        "diffusive", 2.0, 60.0, 6.0,
                        {"gamma": 1.4, "mu": 3.52 / (1.225 * 340.2), "kappa": 4980.0 / (287.0 * 1.225 * 340.2),
                         "R_gas": 1.0}),
+    "mhd2048": Preset("mhd2048", "mhd_trk2d", "D2Q5", 2048, "f32", 100,
+                      "acoustic", 0.025, 160.0, 4.0,
+                      {"gamma": 1.4, "mu": 4.165 / (1.225 * 340.0), "kappa": 4.165 / (1.225 * 340.0),
+                       "eta": 3.4 / 340.0}),
 }
 
 # Seeds of the random fields.
@@ -286,6 +290,24 @@ def cnsf2d_initial(n: int, gamma: float = 1.4):
     Ey = ry / (gamma - 1.0) + ry * kin + rho * v * vy
     return np.stack([rho, rho * u, rho * v, E, rx, ry, rx * u, ry * u, rx * v + rho * vx, ry * v + rho * vy,
                      Ex, Ey])
+
+
+def mhd_initial(n: int, gamma: float = 1.4):
+    """The paper's resistive MHD state at t = 0 in units rho0 = cs = 1:
+    rho = 1 + 0.3 sin(2 pi x) cos(2 pi y), u = v = 3, B = (0.5, 0.5),
+    p = 1/gamma + (rho - 1); conserved fields and their analytic gradients
+    (rho, m0, m1, E, B0, B1, G_rho, G_m0, G_m1, G_E, G_B0, G_B1), [18, n, n]."""
+    X, Y = grid2(n)
+    k = 2.0 * math.pi
+    sx, cx, sy, cy = np.sin(k * X), np.cos(k * X), np.sin(k * Y), np.cos(k * Y)
+    rho = 1.0 + 0.3 * sx * cy
+    rx, ry = 0.3 * k * cx * cy, -0.3 * k * sx * sy
+    p = 1.0 / gamma + (rho - 1.0)
+    E = p / (gamma - 1.0) + 9.0 * rho + 0.25
+    c = 1.0 / (gamma - 1.0) + 9.0
+    z = np.zeros_like(rho)
+    return np.stack([rho, 3.0 * rho, 3.0 * rho, E, z + 0.5, z + 0.5, rx, ry, 3.0 * rx, 3.0 * ry, 3.0 * rx, 3.0 * ry,
+                     c * rx, c * ry, z, z, z, z])
 
 
 def neohooke_initial(n: int, seeds=SEED_DISPLACEMENT):

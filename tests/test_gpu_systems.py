@@ -184,3 +184,25 @@ def test_cnsf2d_matches_oracle(lattice, shape, storage, tol):
     print("rel L2", {k: f"{v:.3e}" for k, v in errs.items()})
     for k, v in errs.items():
         assert v <= tol, k
+
+
+MHD_MU = 4.165 / (1.225 * 340.0)
+MHD_ETA = 3.4 / 340.0
+
+
+@pytest.mark.parametrize("lattice,shape,storage,tol", [
+    ("D2Q5", (64, 64), "f32", 1e-6), ("D2Q5", (40, 56), "f32", 1e-6), ("D2Q5", (48, 48), "f64", 1e-12)])
+def test_mhd_matches_oracle(lattice, shape, storage, tol):
+    """The paper's resistive MHD state at t = 0 (Mach 3 per axis, B = 0.5 cs
+    per axis, exact conserved-field trackers; mu = K = eta = 0.01 read with
+    rho0 = cs = 1), acoustic recipe f = 0.025, tau_R = 160 (single) / 140
+    (double), g_tau = 4, unforced; 18 fields, so the wide-block launch."""
+    print(f"mhd_trk2d {lattice} {storage} {shape} 400 steps", flush=True)
+    fQ, _ = mms.mhd_paper(MHD_MU, MHD_MU, MHD_ETA)
+    Qg, Qo = run_pair("mhd_trk2d", lattice, shape, 0.025, 140.0 if storage == "f64" else 160.0, 400, storage,
+                      {"gamma": GAMMA, "mu": MHD_MU, "kappa": MHD_MU, "eta": MHD_ETA, "g_tau": 4.0}, fQ)
+    errs = {"rho": rel(Qg[0], Qo[0]), "m": rel(Qg[1:3], Qo[1:3]), "E": rel(Qg[3], Qo[3]),
+            "B": rel(Qg[4:6], Qo[4:6]), "G": rel(Qg[6:], Qo[6:])}
+    print("rel L2", {k: f"{v:.3e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= tol, k
