@@ -29,19 +29,22 @@ from .build import LIB, build
 
 SYSTEMS = {"advdiff_trk2d": 0, "swe2d": 1, "neohooke2d": 2, "nsf3d_trk17": 3, "burgers2d": 4, "euler2d": 5,
            "maxwell2d": 6, "allencahn_trk2d": 7, "relhydro2d": 8, "nse_trk2d": 9,
-           "cnsf_trk2d": 10, "mhd_trk2d": 11}
+           "cnsf_trk2d": 10, "mhd_trk2d": 11, "hcnsf3d_trk14": 12}
 LATTICES = {"D2Q5": 0, "D2Q9": 1, "D3Q7": 2}
 LATTICE_DIM = {"D2Q5": 2, "D2Q9": 2, "D3Q7": 3}
 SYSTEM_DIM = {"advdiff_trk2d": 2, "swe2d": 2, "neohooke2d": 2, "nsf3d_trk17": 3, "burgers2d": 2, "euler2d": 2,
               "maxwell2d": 2, "allencahn_trk2d": 2, "relhydro2d": 2, "nse_trk2d": 2,
-              "cnsf_trk2d": 2, "mhd_trk2d": 2}
+              "cnsf_trk2d": 2, "mhd_trk2d": 2, "hcnsf3d_trk14": 3}
 PARAM_INDEX = {"g": 0, "ax": 1, "ay": 2, "az": 3, "nu": 4, "R": 5, "tau_grad": 6,
                "gamma": 7, "mu": 8, "kappa": 9, "rho0": 10, "mu_s": 11, "lambda_s": 12,
                "c": 13, "cs_phys": 14, "R_gas": 15,
                "eta": 4}
 TRACKER_FIELDS = {"advdiff_trk2d": range(1, 3), "nsf3d_trk17": range(5, 17), "allencahn_trk2d": range(1, 3),
                   "nse_trk2d": range(3, 7), "cnsf_trk2d": range(4, 12),
-                  "mhd_trk2d": range(6, 18)}
+                  "mhd_trk2d": range(6, 18), "hcnsf3d_trk14": range(5, 14)}
+# components of the per-cell coefficient field b ([NB, ...]): the homogenized
+# NSF system's (alpha, u_s); otherwise one per dimension (SWE: grad z_b)
+COEF_COMPONENTS = {"hcnsf3d_trk14": 4}
 MAXK = 18
 
 
@@ -66,10 +69,10 @@ def _load():
         P = ctypes.POINTER
         d = P(ctypes.c_double)
         c = P(_Cfg)
-        lib.oracle_init.argtypes = [c, d, d]
+        lib.oracle_init.argtypes = [c, d, d, d]
         lib.oracle_moments.argtypes = [c, d, d]
         lib.oracle_step.argtypes = [c, d, d, d, d]
-        lib.oracle_flux.argtypes = [c, d, d]
+        lib.oracle_flux.argtypes = [c, d, d, d]
         lib.oracle_source.argtypes = [c, d, d, d]
         lib.oracle_adjoint_step.argtypes = [c, d, d, d, d, d]
         lib.oracle_init_adjoint.argtypes = [c, d, d, d]
@@ -161,10 +164,11 @@ class Oracle:
         self.nsteps = 0
 
     # ---- single-state evaluations -------------------------------------
-    def flux(self, q):
+    def flux(self, q, b=None):
         q = np.ascontiguousarray(q, dtype=np.float64)
+        bb = None if b is None else np.ascontiguousarray(b, dtype=np.float64)
         out = np.zeros(self.K * 3)
-        self.lib.oracle_flux(ctypes.byref(self.cfg), _ptr(q), _ptr(out))
+        self.lib.oracle_flux(ctypes.byref(self.cfg), _ptr(q), _ptr(bb), _ptr(out))
         return out.reshape(self.K, 3)
 
     def source(self, q, b=None):
@@ -175,9 +179,12 @@ class Oracle:
         return out
 
     # ---- fields ---------------------------------------------------------
-    def init(self, Qf):
+    def init(self, Qf, b=None):
+        """Populations at the (shifted) equilibrium of the fields ``Qf``; ``b``
+        is the per-cell coefficient field at t = 0 when the flux reads one."""
         Qf = np.ascontiguousarray(Qf, dtype=np.float64).reshape((self.K,) + self.shape)
-        self.lib.oracle_init(ctypes.byref(self.cfg), _ptr(Qf), _ptr(self.f))
+        bb = None if b is None else np.ascontiguousarray(b, dtype=np.float64)
+        self.lib.oracle_init(ctypes.byref(self.cfg), _ptr(Qf), _ptr(bb), _ptr(self.f))
         self.t = 0.0
         self.nsteps = 0
 
@@ -190,14 +197,17 @@ class Oracle:
     def step(self, n=1, source=None, b=None, history=None):
         """Advance n steps.  ``source(t)`` returns an explicit [K, ...] source
         evaluated at the given time (called with t_n + dt/2); ``b`` is the
-        per-cell coefficient field [D, ...]; ``history`` (a list) receives a
-        copy of the pre-collision populations of every step taken."""
-        bb = None if b is None else np.ascontiguousarray(b, dtype=np.float64)
+        per-cell coefficient field [NB, ...], or a function of time giving it
+        (called with t_n + dt/2, like the source); ``history`` (a list)
+        receives a copy of the pre-collision populations of every step taken."""
+        bb = None if (b is None or callable(b)) else np.ascontiguousarray(b, dtype=np.float64)
         out = np.empty_like(self.f)
         for _ in range(n):
             S = None
             if source is not None:
                 S = np.ascontiguousarray(source(self.t + 0.5 * self.dt), dtype=np.float64)
+            if callable(b):
+                bb = np.ascontiguousarray(b(self.t + 0.5 * self.dt), dtype=np.float64)
             if history is not None:
                 history.append(self.f.copy())
             self.lib.oracle_step(ctypes.byref(self.cfg), _ptr(self.f), _ptr(out), _ptr(S), _ptr(bb))

@@ -34,7 +34,7 @@
 
 enum { SYS_ADVDIFF = 0, SYS_SWE = 1, SYS_NEOHOOKE = 2, SYS_NSF17 = 3, SYS_BURGERS = 4, SYS_EULER = 5,
        SYS_MAXWELL = 6, SYS_ALLENCAHN = 7, SYS_RELHYDRO = 8, SYS_NSE = 9, SYS_CNSF2D = 10,
-       SYS_MHD = 11 };
+       SYS_MHD = 11, SYS_HCNSF = 12 };
 enum { LAT_D2Q5 = 0, LAT_D2Q9 = 1, LAT_D3Q7 = 2 };
 enum {
     P_G = 0, P_AX, P_AY, P_AZ, P_NU, P_R, P_TAUG, P_GAMMA, P_MU, P_KAPPA,
@@ -108,9 +108,16 @@ static int system_K(int sys)
     case SYS_NSE: return 7;
     case SYS_CNSF2D: return 12;
     case SYS_MHD: return 18;
+    case SYS_HCNSF: return 14;
     }
     return 0;
 }
+
+/* Components of the per-cell coefficient field: the prescribed porosity and
+ * solid velocity (alpha, u_s) of the homogenized NSF system, otherwise one
+ * per dimension (SWE: grad z_b). */
+static int system_nb(int sys, int D) { return sys == SYS_HCNSF ? 4 : D; }
+#define MAXB 4
 
 /* ---- scalar-type instantiations of the cell arithmetic ---- */
 #define T double
@@ -139,7 +146,7 @@ static void reference_flux(const oracle_cfg *cfg, int K, double *F0)
     memset(F0, 0, sizeof(double) * MAXK * 3);
     memset(Phi, 0, sizeof Phi);
     if (!cfg->shifted) return;
-    flux_re(cfg->system, cfg->par, cfg->Q0, Phi);
+    flux_re(cfg->system, cfg->par, cfg->Q0, NULL, Phi);
     for (int k = 0; k < K; ++k)
         for (int a = 0; a < 3; ++a) F0[k * 3 + a] = Phi[k][a];
 }
@@ -151,12 +158,13 @@ static inline long wrap(long v, long n) { return ((v % n) + n) % n; }
 int oracle_num_fields(int sys) { return system_K(sys); }
 int oracle_num_velocities(int lat) { return lattice_get(lat).Q; }
 
-/* Physical flux Phi (K x 3, row-major) and source S (K) at one state Q. */
-void oracle_flux(const oracle_cfg *cfg, const double *Q, double *Phi_out)
+/* Physical flux Phi (K x 3, row-major) and source S (K) at one state Q;
+ * b: the cell's coefficient values (system_nb of them) or NULL. */
+void oracle_flux(const oracle_cfg *cfg, const double *Q, const double *b, double *Phi_out)
 {
     double Phi[MAXK][3];
     memset(Phi, 0, sizeof Phi);
-    flux_re(cfg->system, cfg->par, Q, Phi);
+    flux_re(cfg->system, cfg->par, Q, b, Phi);
     const int K = system_K(cfg->system);
     for (int k = 0; k < K; ++k)
         for (int a = 0; a < 3; ++a) Phi_out[k * 3 + a] = Phi[k][a];
@@ -169,8 +177,9 @@ void oracle_source(const oracle_cfg *cfg, const double *Q, const double *b, doub
 
 /* Equilibrium initialisation: f*_{k,i}(x) = w_i [ (Q_k - Q0_k)
  *   + (lam/cs2) c_i . (Phi_k(Q) - F0_k) ] at every cell, from fields
- * Q[k*C + cell] (SoA).  Output f[(k*Qn + i)*C + cell]. */
-void oracle_init(const oracle_cfg *cfg, const double *Qf, double *f)
+ * Q[k*C + cell] (SoA) and the coefficient field (nb*C, may be NULL).
+ * Output f[(k*Qn + i)*C + cell]. */
+void oracle_init(const oracle_cfg *cfg, const double *Qf, const double *bfield, double *f)
 {
     const lattice L = lattice_get(cfg->lattice);
     const int K = system_K(cfg->system);
@@ -179,10 +188,13 @@ void oracle_init(const oracle_cfg *cfg, const double *Qf, double *f)
     reference_flux(cfg, K, F0);
 #pragma omp parallel for schedule(static)
     for (long cell = 0; cell < C; ++cell) {
-        double Q[MAXK], Phi[MAXK][3];
+        double Q[MAXK], Phi[MAXK][3], b[MAXB];
         memset(Phi, 0, sizeof Phi);
         for (int k = 0; k < K; ++k) Q[k] = Qf[k * C + cell];
-        flux_re(cfg->system, cfg->par, Q, Phi);
+        const int nb = system_nb(cfg->system, L.D);
+        if (bfield)
+            for (int a = 0; a < nb; ++a) b[a] = bfield[a * C + cell];
+        flux_re(cfg->system, cfg->par, Q, bfield ? b : NULL, Phi);
         for (int k = 0; k < K; ++k)
             for (int i = 0; i < L.Q; ++i) {
                 double cdot = 0.0;
@@ -212,8 +224,8 @@ void oracle_moments(const oracle_cfg *cfg, const double *f, double *Qf)
 /* One collide-and-stream step (eq. lbe_update), push form:
  *   f_out_{k,i}(x + c_i mod N) = post_{k,i}(x).
  * S_ext (K*C, may be NULL): explicit source added to S_k, e.g. the
- * manufactured-solution forcing at t + dt/2.  b (D*C, may be NULL):
- * per-cell coefficient field for the system's source (SWE: grad z_b). */
+ * manufactured-solution forcing at t + dt/2.  b (nb*C, may be NULL):
+ * per-cell coefficient field (SWE: grad z_b; homogenized NSF: alpha, u_s). */
 void oracle_step(const oracle_cfg *cfg, const double *fin, double *fout,
                  const double *S_ext, const double *bfield)
 {
@@ -226,13 +238,13 @@ void oracle_step(const oracle_cfg *cfg, const double *fin, double *fout,
 #pragma omp parallel for schedule(static)
     for (long cell = 0; cell < C; ++cell) {
         const long x = cell % nx, y = (cell / nx) % ny, z = cell / (nx * ny);
-        double f[MAXK * MAXQ], post[MAXK * MAXQ], Sx[MAXK], b[3];
+        double f[MAXK * MAXQ], post[MAXK * MAXQ], Sx[MAXK], b[MAXB];
         for (int k = 0; k < K; ++k)
             for (int i = 0; i < L.Q; ++i) f[k * L.Q + i] = fin[((long)k * L.Q + i) * C + cell];
         if (S_ext)
             for (int k = 0; k < K; ++k) Sx[k] = S_ext[k * C + cell];
         if (bfield)
-            for (int a = 0; a < L.D; ++a) b[a] = bfield[a * C + cell];
+            for (int a = 0; a < system_nb(cfg->system, L.D); ++a) b[a] = bfield[a * C + cell];
         collide_cell_re(cfg, &L, K, F0, f, bfield ? b : NULL, S_ext ? Sx : NULL, post);
         for (int i = 0; i < L.Q; ++i) {
             const long xd = wrap(x + L.c[i][0], nx);
@@ -266,7 +278,7 @@ void oracle_adjoint_step(const oracle_cfg *cfg, const double *lam_next, double *
 #pragma omp parallel for schedule(static)
     for (long cell = 0; cell < C; ++cell) {
         const long x = cell % nx, y = (cell / nx) % ny, z = cell / (nx * ny);
-        double complex f[MAXK * MAXQ], post[MAXK * MAXQ], b[3];
+        double complex f[MAXK * MAXQ], post[MAXK * MAXQ], b[MAXB];
         double mu[MAXK * MAXQ];
         for (int k = 0; k < K; ++k)
             for (int i = 0; i < L.Q; ++i) {
@@ -276,7 +288,8 @@ void oracle_adjoint_step(const oracle_cfg *cfg, const double *lam_next, double *
                 const long zs = wrap(z + L.c[i][2], nz);
                 mu[k * L.Q + i] = lam_next[((long)k * L.Q + i) * C + (zs * ny + ys) * nx + xs];
             }
-        for (int a = 0; a < 3; ++a) b[a] = (bfield && a < L.D) ? bfield[a * C + cell] : 0.0;
+        const int nb = system_nb(cfg->system, L.D);
+        for (int a = 0; a < MAXB; ++a) b[a] = (bfield && a < nb) ? bfield[a * C + cell] : 0.0;
         for (int n = 0; n < KQ; ++n) {
             const double complex keep = f[n];
             f[n] = keep + I * h;
@@ -288,7 +301,7 @@ void oracle_adjoint_step(const oracle_cfg *cfg, const double *lam_next, double *
             lam_out[((long)k * L.Q + i) * C + cell] = acc;
         }
         if (grad_b && bfield) {
-            for (int a = 0; a < L.D; ++a) {
+            for (int a = 0; a < nb; ++a) {
                 const double complex keep = b[a];
                 b[a] = keep + I * h;
                 collide_cell_cx(cfg, &L, K, F0, f, b, NULL, post);
@@ -320,7 +333,7 @@ void oracle_init_adjoint(const oracle_cfg *cfg, const double *lam0, const double
             const double complex keep = Q[m];
             Q[m] = keep + I * h;
             memset(Phi, 0, sizeof Phi);
-            flux_cx(cfg->system, cfg->par, Q, Phi);
+            flux_cx(cfg->system, cfg->par, Q, NULL, Phi);
             double acc = 0.0;
             for (int k = 0; k < K; ++k)
                 for (int i = 0; i < L.Q; ++i) {

@@ -28,6 +28,8 @@ Cases:
 * ``cnsf2d_paper`` -- the paper's 2D compressible NSF MMS (Mach 3 / 2),
   trackers exact.
 * ``mhd_paper``  -- the paper's resistive-MHD MMS, trackers exact.
+* ``hcnsf_paper`` -- the paper's 3D homogenized-NSF MMS (14 fields, Ma 0.5,
+  amplitude 0.2) with its prescribed porosity and solid velocity.
 * ``nsf17``      -- the 3D compressible NSF manufactured solution with the
   shapes of the paper's homogenized-NSF MMS (porosity 1), conserved rows
   forced; tracker rows are forced only when ``force_trackers`` is set.
@@ -429,6 +431,81 @@ def nsf17(gamma, rho0, p0, u0, amp, mu, kappa, tau_grad, force_trackers=False):
     fQ = sp.lambdify((X, Y, Z, T), Q, "numpy", cse=True)
     fS = sp.lambdify((X, Y, Z, T), res, "numpy", cse=True)
     return _wrap3(fQ), _wrap3(fS)
+
+
+# -------------------------------------------------------------- HCNSF ----
+def hcnsf_coef_exprs():
+    """Prescribed coefficient fields of the paper's homogenized-NSF MMS
+    (supplement): solid velocity u_s = rotation (amplitude 0.2) + uniform
+    translation c = (0.1, -0.1, 0.05) + oscillation (amplitude 0.1), and the
+    porosity alpha = 1/2 + [sin k xi_0 + sin k xi_1 + sin k xi_2
+    + 2 sin k xi_0 sin k xi_1 sin k xi_2] / 10 advected along xi = x - d,
+    d_i = r_i(x) sin t + c_i t, with r the rotation's spatial profile
+    (the reading of the printed displacement).  Velocities in units of cs."""
+    k = PI2
+    c = (sp.Rational(1, 10), -sp.Rational(1, 10), sp.Rational(1, 20))
+    a2 = sp.Rational(1, 5)
+    r = [a2 * sp.sin(k * X) * sp.cos(k * Y) * sp.cos(k * Z),
+         -a2 * sp.cos(k * X) * sp.sin(k * Y) * sp.cos(k * Z),
+         a2 * sp.cos(k * X) * sp.cos(k * Y) * sp.sin(k * Z)]
+    us = [r[0] * sp.cos(T) + c[0] + sp.sin(T) * sp.cos(k * Z) / 10,
+          r[1] * sp.cos(T) + c[1] + sp.cos(T) * sp.cos(k * X) / 10,
+          r[2] * sp.sin(T) + c[2] + sp.sin(T) * sp.cos(k * Y) / 10]
+    xi = [v - (r[i] * sp.sin(T) + c[i] * T) for i, v in enumerate((X, Y, Z))]
+    s = [sp.sin(k * v) for v in xi]
+    alpha = sp.Rational(1, 2) + (s[0] + s[1] + s[2] + 2 * s[0] * s[1] * s[2]) / 10
+    return alpha, us
+
+
+def hcnsf_exact_exprs(gamma=1.4, amp=0.2, mach=0.5):
+    """14 exact fields of the paper's homogenized-NSF MMS in units
+    rho0 = cs = 1 (p0 = 1, mean sound speed sqrt(gamma), drift Ma sqrt(gamma)):
+    rho, rho u, E, sym grad u as (00, 11, 22, 01, 02, 12), grad T."""
+    gm = sp.Float(gamma)
+    rho, u, p, E, Tm, G, GT = nsf_exact_exprs(gm, 1, 1, sp.Float(mach) * sp.sqrt(gm), amp)
+    sym = [(G[a][b] + G[b][a]) / 2 for a, b in ((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))]
+    return [rho] + [rho * u[a] for a in range(3)] + [E] + sym + list(GT)
+
+
+def hcnsf_flux_source_exprs(Q, b, gamma, mu, kappa, eta):
+    """Phi (conserved rows, 5 x 3) and S (5) of the homogenized NSF system in
+    tensor form (paper Sec. 3), at the exact trackers."""
+    alpha, us = b[0], b[1:4]
+    rho, m, E = Q[0], Q[1:4], Q[4]
+    idx = {(0, 0): 5, (1, 1): 6, (2, 2): 7, (0, 1): 8, (0, 2): 9, (1, 2): 10}
+    G = [[Q[idx[(min(a, c), max(a, c))]] for c in range(3)] for a in range(3)]
+    GT = Q[11:14]
+    u = [m[a] / rho for a in range(3)]
+    p = (gamma - 1) * (E - (m[0] * u[0] + m[1] * u[1] + m[2] * u[2]) / 2)
+    trG = G[0][0] + G[1][1] + G[2][2]
+    tau = [[mu * (2 * G[a][c] - (sp.Rational(2, 3) * trG if a == c else 0)) for c in range(3)] for a in range(3)]
+    Phi = [[m[c] for c in range(3)]]
+    for a in range(3):
+        Phi.append([m[a] * u[c] + (p if a == c else 0) - alpha * tau[a][c] for c in range(3)])
+    Phi.append([(E + p) * u[c] - alpha * sum(tau[c][d] * u[d] for d in range(3)) - alpha * kappa * GT[c]
+                for c in range(3)])
+    drag = (1 - alpha) / eta
+    Sm = [drag * (rho * us[a] - m[a]) for a in range(3)]
+    S = [0] + Sm + [sum(Sm[a] * u[a] for a in range(3))]
+    return Phi, S
+
+
+@functools.lru_cache(maxsize=None)
+def hcnsf_paper(mu, kappa, eta, gamma=1.4, amp=0.2, mach=0.5):
+    """(exact -> [14, ...], forcing -> [14, ...], coefficients -> [4, ...]),
+    all functions of (x, y, z, t): conserved rows forced with the flux and the
+    drag source at the exact trackers and the prescribed (alpha, u_s),
+    tracker rows not."""
+    Q = hcnsf_exact_exprs(gamma, amp, mach)
+    alpha, us = hcnsf_coef_exprs()
+    b = [alpha] + us
+    Phi, S = hcnsf_flux_source_exprs(Q, b, sp.Float(gamma), sp.Float(mu), sp.Float(kappa), sp.Float(eta))
+    coords = (X, Y, Z)
+    res = [sp.diff(Q[k], T) + _div(Phi[k], coords) - S[k] for k in range(5)] + [sp.Integer(0)] * 9
+    fQ = sp.lambdify((X, Y, Z, T), Q, "numpy", cse=True)
+    fS = sp.lambdify((X, Y, Z, T), res, "numpy", cse=True)
+    fB = sp.lambdify((X, Y, Z, T), b, "numpy", cse=True)
+    return _wrap3(fQ), _wrap3(fS), _wrap3(fB)
 
 
 # ------------------------------------------------------------- helpers ----

@@ -1291,3 +1291,152 @@ def test_mhd_mms_at_128():
     for k in ("B", "E", "rho", "m"):
         s = g[f"mhd_double_{k}_eoc_L2"]
         assert 2 ** (2 * s - 0.3) < e[k] / g[f"mhd_double_{k}_relL2_N512"] < 2 ** (2 * s + 0.3), k
+
+
+# -------------------------------------------------------------- HCNSF ----
+HCNSF_PRINTED_ROW = (0, 1, 2, 3, 4, 10, 5, 6, 11, 12, 13, 7, 8, 9)   # this oracle's row k -> printed row
+
+
+def _hcnsf_oracle(n=4, dt=0.004, g_tau=3.0, params=None):
+    par = {"gamma": 1.4, "mu": 0.037, "kappa": 0.11, "eta": 0.13}
+    par.update(params or {})
+    u0 = 0.5 * math.sqrt(1.4)
+    return oracle.Oracle("hcnsf3d_trk14", "D3Q7", (n, n, n), dt, 1.0 / n, 0.6, g_tau, par,
+                         Q0=[1.0, u0, u0, u0, 2.5 + 1.5 * u0 * u0] + [0.0] * 9)
+
+
+def test_hcnsf_flux_source_match_printed_expansion():
+    """Supplement, 3D homogenized NSF: the printed 14-field flux (shared-
+    subexpression form) and drag source at random states, porosities and
+    solid velocities; printed state order (G_u11, G_u22, G_T, G_u00, S_u01,
+    S_u02, S_u12 after E) mapped to this oracle's (sym grad u as 00, 11, 22,
+    01, 02, 12, then grad T)."""
+    o = _hcnsf_oracle()
+    tg, gm, mu, K, eta = o.params["tau_grad"], 1.4, 0.037, 0.11, 0.13
+    rng = np.random.default_rng(81)
+    for _ in range(30):
+        rho = rng.uniform(0.7, 1.3)
+        m = rng.uniform(-1, 1, 3)
+        E = rng.uniform(2.5, 4.0)
+        Gs = rng.uniform(-2, 2, 6)
+        GT = rng.uniform(-2, 2, 3)
+        alpha = rng.uniform(0, 1)
+        us = rng.uniform(-0.5, 0.5, 3)
+        q = np.concatenate([[rho], m, [E], Gs, GT])
+        b = np.concatenate([[alpha], us])
+        ref = _hcnsf_printed(rho, m[0], m[1], m[2], E, Gs[1], Gs[2], GT[0], GT[1], GT[2], Gs[0], Gs[3],
+                             Gs[4], Gs[5], gm, mu, K, tg, alpha=alpha)
+        got = o.flux(q, b)
+        scale = max(1.0, np.abs(ref).max())
+        for k in range(14):
+            assert np.abs(got[k] - ref[HCNSF_PRINTED_ROW[k]]).max() < 1e-13 * scale, k
+        S = o.source(q, b)
+        Sp = [0.0] + [-alpha * us[a] * rho / eta + alpha * m[a] / eta + us[a] * rho / eta - m[a] / eta
+                      for a in range(3)]
+        Sp.append(sum(-alpha * us[a] * m[a] / eta + alpha * m[a] ** 2 / (eta * rho) + us[a] * m[a] / eta
+                      - m[a] ** 2 / (eta * rho) for a in range(3)))
+        assert np.allclose(S[:5], Sp, rtol=1e-13, atol=1e-14)
+        assert np.allclose(S[5:], -q[5:] / tg, rtol=1e-14, atol=0)
+    # without a coefficient field: pure fluid (alpha = 1, no drag)
+    got = o.flux(q)
+    ref = _hcnsf_printed(rho, m[0], m[1], m[2], E, Gs[1], Gs[2], GT[0], GT[1], GT[2], Gs[0], Gs[3],
+                         Gs[4], Gs[5], gm, mu, K, tg, alpha=1.0)
+    for k in range(14):
+        assert np.abs(got[k] - ref[HCNSF_PRINTED_ROW[k]]).max() < 1e-13 * max(1.0, np.abs(ref).max())
+    assert np.abs(o.source(q)[:5]).max() == 0.0
+
+
+def test_hcnsf_mms_fields_and_coefficients():
+    """The 14 exact fields: conserved rows equal the inputs module's 3D NSF
+    fields at the printed working point (Ma 0.5, A 0.2; pinned to the printed
+    expansion above), the tracker rows equal central differences of the exact
+    velocity and temperature (sym grad u, grad T).  The coefficient fields at
+    t = 0 (no displacement yet) equal the printed porosity sinusoid and solid
+    velocity, and the porosity stays within [0, 1] as printed."""
+    fQ, _, fB = mms.hcnsf_paper(0.01, 0.01, 0.1)
+    n, t = 6, 0.41
+    X, Y, Z = inputs.grid3(n)
+    Q = fQ(X, Y, Z, t)
+    assert np.abs(Q[:5] - inputs.nsf_exact(n, t, inputs.NsfMms(mach=0.5, amp=0.2))[:5]).max() < 1e-13
+    h = 1e-5
+
+    def prim(Xs, Ys, Zs):
+        q = fQ(Xs, Ys, Zs, t)
+        u = q[1:4] / q[0]
+        p = 0.4 * (q[4] - 0.5 * (q[1] * u[0] + q[2] * u[1] + q[3] * u[2]))
+        return u, p / q[0]
+
+    grads_u, grads_T = [], []
+    for d in range(3):
+        e = [np.zeros_like(X)] * 3
+        e = [e[i] + (h if i == d else 0.0) for i in range(3)]
+        up, Tp = prim(X + e[0], Y + e[1], Z + e[2])
+        um, Tm = prim(X - e[0], Y - e[1], Z - e[2])
+        grads_u.append((up - um) / (2 * h))
+        grads_T.append((Tp - Tm) / (2 * h))
+    Gfd = [[grads_u[b][a] for b in range(3)] for a in range(3)]      # d u_a / d x_b
+    for s, (a, b) in enumerate(((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))):
+        assert np.abs(Q[5 + s] - 0.5 * (Gfd[a][b] + Gfd[b][a])).max() < 1e-7
+    for a in range(3):
+        assert np.abs(Q[11 + a] - grads_T[a]).max() < 1e-7
+    B0 = fB(X, Y, Z, 0.0)
+    k = 2 * np.pi
+    s0, s1, s2 = np.sin(k * X), np.sin(k * Y), np.sin(k * Z)
+    assert np.abs(B0[0] - (0.5 + (s0 + s1 + s2 + 2 * s0 * s1 * s2) / 10)).max() < 1e-14
+    c0, c1, c2 = np.cos(k * X), np.cos(k * Y), np.cos(k * Z)
+    assert np.abs(B0[1] - (0.2 * s0 * c1 * c2 + 0.1)).max() < 1e-14
+    assert np.abs(B0[2] - (-0.2 * c0 * s1 * c2 - 0.1 + 0.1 * c0)).max() < 1e-14
+    assert np.abs(B0[3] - 0.05).max() < 1e-14
+    rng = np.random.default_rng(82)
+    pts = rng.uniform(0, 1, (4, 2000))
+    a = fB(pts[0], pts[1], pts[2], 3 * pts[3])[0]
+    assert a.min() >= 0.0 and a.max() <= 1.0
+
+
+def _hcnsf_errors(n):
+    g = _gold("mms_printed.json")
+    rec, si = g["recipes"]["hcnsf_double"], g["hcnsf_mms_SI"]
+    # nondimensional reading (rho0 = cs = L = 1): mu, kappa / (rho0 cs L), eta cs / L
+    mu = si["mu"] / (si["rho0"] * si["cs"])
+    K = si["kappa"] / (si["rho0"] * si["cs"])
+    eta = si["eta"] * si["cs"]
+    fQ, fS, fB = mms.hcnsf_paper(mu, K, eta, gamma=si["gamma"])
+    dx, dt, tau = oracle.recipe(n, "acoustic", rec["f"], rec["tau_r"])
+    X, Y, Z = inputs.grid3(n)
+    u0 = 0.5 * math.sqrt(si["gamma"])
+    o = oracle.Oracle("hcnsf3d_trk14", "D3Q7", (n, n, n), dt, dx, tau, rec["g_tau"],
+                      {"gamma": si["gamma"], "mu": mu, "kappa": K, "eta": eta},
+                      Q0=[1.0, u0, u0, u0, 1 / (si["gamma"] - 1) + 1.5 * u0 * u0] + [0.0] * 9)
+    o.init(fQ(X, Y, Z, 0.0), b=fB(X, Y, Z, 0.0))
+    o.step(int(round(1.0 / dt)), source=lambda t: fS(X, Y, Z, t), b=lambda t: fB(X, Y, Z, t))
+    Qn, Qe = o.moments(), fQ(X, Y, Z, o.t)
+    return {"rho": mms.rel_l2(Qn[0], Qe[0]), "E": mms.rel_l2(Qn[4], Qe[4]),
+            "m": math.sqrt(sum(mms.rel_l2(Qn[a], Qe[a]) ** 2 for a in (1, 2, 3)))}
+
+
+def test_hcnsf_mms_magnitude_at_32():
+    """3D homogenized NSF MMS (Ma 0.5, A 0.2, alpha over [0, 1] advected with
+    the solid, read with rho0 = cs = 1: mu = kappa = 0.01, eta = 0.1) under
+    the acoustic recipe f = 0.05, tau_R = 10, g_tau = 3.  The N = 32 errors of
+    rho, rho u and E sit 2^(3 x printed LSQ order +- 0.2) above the printed
+    N = 256 errors (oracle: 2^5.64, 2^5.90, 2^5.40)."""
+    g = _gold("mms_printed.json")
+    e = _hcnsf_errors(32)
+    for k in ("rho", "m", "E"):
+        s = g[f"hcnsf_double_{k}_eoc_L2"]
+        assert 2 ** (3 * s - 0.2) < e[k] / g[f"hcnsf_double_{k}_relL2_N256"] < 2 ** (3 * s + 0.2), k
+
+
+@pytest.mark.slow
+def test_hcnsf_mms_at_64():
+    """N = 64 errors sit 2^(2 x printed order +- 0.3) above the printed
+    N = 256 errors (oracle: rho 2^3.93, rho u 2^4.00, E 2^3.83; 32 -> 64
+    orders 1.71, 1.91, 1.56, pre-asymptotic below the printed LSQ orders).
+    The tracker error G_u stays unpinned: under neither the Euclidean norm of
+    per-component errors (0.21) nor the combined norm (0.086) does it sit on
+    the printed value carried back at the printed order (0.13)."""
+    g = _gold("mms_printed.json")
+    e = _hcnsf_errors(64)
+    for k in ("rho", "m", "E"):
+        s = g[f"hcnsf_double_{k}_eoc_L2"]
+        assert 2 ** (2 * s - 0.3) < e[k] / g[f"hcnsf_double_{k}_relL2_N256"] < 2 ** (2 * s + 0.3), k
