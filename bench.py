@@ -168,8 +168,10 @@ def probe_pattern(torch, lbm, n, fields=3, reps=20):
 def extra_runs(torch, lbm, inputs):
     out = {}
 
-    def one(name, preset, n, storage, steps, bytes_per_cell, init):
+    def one(name, preset, n, storage, steps, bytes_per_cell, init, coef=None):
         g = lbm.from_preset(preset, n=n, storage=storage)
+        if coef is not None:
+            g.set_field("coef", coef)
         g.init(init)
         g.step(10)
         total, kern = time_steps(torch, g, steps, per_launch=False)
@@ -200,6 +202,10 @@ def extra_runs(torch, lbm, inputs):
     one("cnsf_trk2d_D2Q5_f32_2048", p, 2048, "f32", 100, 480, inputs.cnsf2d_initial(2048))
     p = inputs.PRESETS["mhd2048"]
     one("mhd_trk2d_D2Q5_f32_2048", p, 2048, "f32", 100, 720, inputs.mhd_initial(2048))
+    p = inputs.PRESETS["hcnsf256"]
+    # 2 x 14 x 7 x 4 B of populations + 4 x 4 B of porosity and solid velocity
+    one("hcnsf3d_trk14_D3Q7_f32_256", p, 256, "f32", 50, 800, inputs.hcnsf_exact(256, 0.0),
+        coef=inputs.hcnsf_coefficients(256, 0.0))
     p = inputs.PRESETS["advdiff64"]
     one("advdiff_D2Q5_f64_64", p, 64, "f64", 200, 240, inputs.advdiff_initial(64))
     p = inputs.PRESETS["nsf256"]

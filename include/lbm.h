@@ -91,6 +91,10 @@ enum {                      /* lbm_reduce: what                                 
  *            "mhd_trk2d"     2D resistive MHD (rho, rho u0, rho u1, E, B0, B1;
  *                            B in Alfven units) with conserved-field gradient
  *                            trackers and the Powell source (18 fields), Sec. 3
+ *            "hcnsf3d_trk14" 3D homogenized compressible NSF (rho, rho u, E,
+ *                            sym grad u as 00, 11, 22, 01, 02, 12, grad T;
+ *                            14 fields) with a prescribed per-cell porosity
+ *                            and solid velocity ("coef" field), Sec. 3
  *   Tracker layout (2D): tracker fields follow the conserved fields, two
  *   per tracked field in field order (G_q,0, G_q,1).
  *   lattice: "D2Q5" | "D2Q9" (2D systems) | "D3Q7" (3D systems)
@@ -126,6 +130,7 @@ int lbm_num_velocities(const lbm_state *h);
  *                   R_gas (T = p / (rho R_gas)), g_tau
  *   mhd_trk2d:      gamma, mu (dynamic viscosity), kappa (heat-flux coefficient
  *                   K, with T = p / rho), eta (magnetic diffusivity), g_tau
+ *   hcnsf3d_trk14:  gamma, mu, kappa (T = p / rho), eta (drag time, > 0), g_tau
  *   all:            t0 (initial time) */
 int lbm_set_param(lbm_state *h, const char *name, double v);
 
@@ -151,6 +156,9 @@ int lbm_set_storage(lbm_state *h, int storage);
  * Mach-3 background of the paper's manufactured solution in units
  * rho0 = cs = 1; cnsf_trk2d (1, 3, 2, 1/(gamma (gamma-1)) + 13/2, 0...);
  * mhd_trk2d (1, 3, 3, 1/(gamma (gamma-1)) + 37/4, 1/2, 1/2, 0...);
+ * hcnsf3d_trk14 (1, U0, U0, U0, 1/(gamma-1) + 3/2 U0^2, 0...) with
+ * U0 = sqrt(gamma)/2 (Mach 1/2 per axis, p0 = rho0 = 1; its tracker
+ * entries must be zero: LBM_EINVAL otherwise);
  * relhydro2d (3, 1.2, 1.2); nse_trk2d (1, 0...); burgers2d, maxwell2d,
  * allencahn_trk2d all zeros. */
 int lbm_set_reference(lbm_state *h, const double *Q0);
@@ -168,9 +176,16 @@ size_t lbm_required_bytes(const lbm_state *h, int which);
  * (NULL = default stream).  The library never frees them. */
 int lbm_bind(lbm_state *h, void *pop_a, void *pop_b, void *aux, void *hip_stream);
 
-/* Attach a per-cell device field read by the system's source:
- *   "grad_zb" (swe2d): topography gradient b = grad z_b, [2][cells] in the
- *   arithmetic type (double for F64 storage, float otherwise); NULL detaches. */
+/* Attach a per-cell device field (caller-owned, [NB][cells] in the
+ * arithmetic type: double for F64 storage, float otherwise; NULL detaches):
+ *   "grad_zb" (swe2d, NB = 2): topography gradient b = grad z_b, read by the
+ *            source;
+ *   "coef"   (hcnsf3d_trk14, NB = 4): porosity alpha in [0, 1] and solid
+ *            velocity u_s, read by the flux and the source of every step
+ *            and by lbm_init_moments (attach it before initialising; without
+ *            it every cell is fluid, alpha = 1).  Not with LBM_F16NE.
+ * The caller may rewrite the field between steps (on the bound stream) to
+ * prescribe it in time. */
 int lbm_set_field(lbm_state *h, const char *name, const void *dev_ptr);
 
 /* Initialise the populations at the shifted equilibrium of the given fields

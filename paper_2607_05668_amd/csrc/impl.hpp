@@ -11,7 +11,8 @@
 enum {
     SYS_ADVDIFF = 0, SYS_SWE = 1, SYS_NEOHOOKE = 2, SYS_NSF17 = 3, SYS_BURGERS = 4, SYS_EULER = 5,
     SYS_MAXWELL = 6, SYS_ALLENCAHN = 7, SYS_RELHYDRO = 8, SYS_NSE = 9, SYS_CNSF2D = 10,
-    SYS_MHD = 11
+    SYS_MHD = 11,
+    SYS_HCNSF = 12
 };
 enum { LAT_D2Q5 = 0, LAT_D2Q9 = 1, LAT_D3Q7 = 2 };
 
@@ -90,6 +91,7 @@ const Launchers *lbm_launchers_relhydro(int lat, int storage);
 const Launchers *lbm_launchers_nse(int lat, int storage);
 const Launchers *lbm_launchers_cnsf2d(int lat, int storage);
 const Launchers *lbm_launchers_mhd(int lat, int storage);
+const Launchers *lbm_launchers_hcnsf(int lat, int storage);
 const Launchers *lbm_launchers_ne(int sys, int lat);   // storage LBM_F16NE
 hipError_t lbm_launch_copy(void *dst, const void *src, size_t n, hipStream_t s);
 hipError_t lbm_launch_streams(void *dst, const void *src, int nx, int ny, int fields, hipStream_t s);
@@ -109,6 +111,7 @@ struct lbm_state_impl {
     double c_light = 1.0;
     double cs_phys = 1.0;
     double R_gas = 1.0;
+    double eta_drag = 0.1;                 // homogenized NSF: drag time eta
     int mms_on = 0;
     double mms_amp = 0.05, mms_rho0 = 1.0, mms_p0 = 1.0, mms_u0 = 0.0;
     double t0 = 0.0;

@@ -97,6 +97,7 @@ KParams<R> lbm_state_impl::kparams(double t_half) const
         if (sys == SYS_NSE) trk = SysNSE::tracker(k);
         if (sys == SYS_CNSF2D) trk = SysCNSF2D::tracker(k);
         if (sys == SYS_MHD) trk = SysMHD::tracker(k);
+        if (sys == SYS_HCNSF) trk = SysHCNSF::tracker(k);
         const double om = trk ? omega_t : omega_c;
         p.omega[k] = (R)om;
         p.delta[k] = (R)(2.0 - om);
@@ -121,7 +122,7 @@ KParams<R> lbm_state_impl::kparams(double t_half) const
     d.rho0 = rho0_el;
     d.mu_s = mu_s;
     d.lam_s = lam_s;
-    if (sys == SYS_NSF17) {
+    if (sys == SYS_NSF17 || sys == SYS_HCNSF) {
         const double r0 = Q0[0];
         double k0 = 0.0;
         for (int a = 0; a < 3; ++a) {
@@ -131,10 +132,13 @@ KParams<R> lbm_state_impl::kparams(double t_half) const
         d.p_ref = (gamma - 1.0) * (Q0[4] - k0);
         d.T_ref = d.p_ref / r0;
         d.H_ref = Q0[4] + d.p_ref;
-        const double trG = Q0[5] + Q0[9] + Q0[13];
-        for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b)
-                d.tau_ref[3 * a + b] = mu * (Q0[5 + 3 * a + b] + Q0[5 + 3 * b + a] - (a == b ? 2.0 / 3.0 * trG : 0.0));
+        if (sys == SYS_NSF17) {
+            const double trG = Q0[5] + Q0[9] + Q0[13];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    d.tau_ref[3 * a + b] =
+                        mu * (Q0[5 + 3 * a + b] + Q0[5 + 3 * b + a] - (a == b ? 2.0 / 3.0 * trG : 0.0));
+        }
     }
     if (sys == SYS_SWE || sys == SYS_EULER || sys == SYS_NSE) {
         d.mm0_h0[0] = Q0[1] * Q0[1] / Q0[0];
@@ -157,6 +161,7 @@ KParams<R> lbm_state_impl::kparams(double t_half) const
     }
     d.cs2_phys = cs_phys * cs_phys;
     d.inv_R_gas = 1.0 / R_gas;
+    d.inv_eta = 1.0 / eta_drag;
     if (sys == SYS_EULER || sys == SYS_CNSF2D) {
         d.p_ref = (gamma - 1.0) * (Q0[3] - 0.5 * (Q0[1] * Q0[1] + Q0[2] * Q0[2]) / Q0[0]);
         d.H_ref = Q0[3] + d.p_ref;
@@ -178,6 +183,7 @@ KParams<R> lbm_state_impl::kparams(double t_half) const
     p.phys.cs2_phys = (R)d.cs2_phys;
     p.phys.sq_ref = (R)d.sq_ref;
     p.phys.inv_R_gas = (R)d.inv_R_gas;
+    p.phys.inv_eta = (R)d.inv_eta;
     for (int j = 0; j < 3; ++j) {
         p.phys.mm0_h0[j] = (R)d.mm0_h0[j];
         p.phys.Hu_ref[j] = (R)d.Hu_ref[j];
@@ -232,6 +238,7 @@ const Launchers *lbm_launchers(int sys, int lat, int storage)
     case SYS_NSE: return lbm_launchers_nse(lat, storage);
     case SYS_CNSF2D: return lbm_launchers_cnsf2d(lat, storage);
     case SYS_MHD: return lbm_launchers_mhd(lat, storage);
+    case SYS_HCNSF: return lbm_launchers_hcnsf(lat, storage);
     }
     return nullptr;
 }

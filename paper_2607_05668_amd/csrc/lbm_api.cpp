@@ -45,6 +45,7 @@ int system_id(const char *s)
     if (!std::strcmp(s, "nse_trk2d")) return SYS_NSE;
     if (!std::strcmp(s, "cnsf_trk2d")) return SYS_CNSF2D;
     if (!std::strcmp(s, "mhd_trk2d")) return SYS_MHD;
+    if (!std::strcmp(s, "hcnsf3d_trk14")) return SYS_HCNSF;
     return -1;
 }
 
@@ -57,8 +58,8 @@ int lattice_id(const char *s)
     return -1;
 }
 
-const int kSysK[12] = {3, 3, 6, 17, 1, 4, 3, 3, 3, 7, 12, 18};
-const int kSysD[12] = {2, 2, 2, 3, 2, 2, 2, 2, 2, 2, 2, 2};
+const int kSysK[13] = {3, 3, 6, 17, 1, 4, 3, 3, 3, 7, 12, 18, 14};
+const int kSysD[13] = {2, 2, 2, 3, 2, 2, 2, 2, 2, 2, 2, 2, 3};
 const int kLatQ[3] = {5, 9, 7};
 const int kLatD[3] = {2, 2, 3};
 const double kLatCs2[3] = {1.0 / 3.0, 1.0 / 3.0, 1.0 / 4.0};
@@ -112,6 +113,19 @@ void mhd_default_reference(lbm_state *h)
     h->Q0[5] = 0.5;
 }
 
+// Reference state of the 3D homogenized NSF system: the background of the
+// paper's manufactured solution in units rho0 = cs = 1 (isothermal cs,
+// p0 = 1): drift Ma sqrt(gamma) per axis with Ma = 1/2,
+// E0 = p0 / (gamma - 1) + 3/2 rho0 U0^2, trackers zero.
+void hcnsf_default_reference(lbm_state *h)
+{
+    std::memset(h->Q0, 0, sizeof h->Q0);
+    const double u0 = 0.5 * std::sqrt(h->gamma);
+    h->Q0[0] = 1.0;
+    for (int a = 0; a < 3; ++a) h->Q0[1 + a] = u0;
+    h->Q0[4] = 1.0 / (h->gamma - 1.0) + 1.5 * u0 * u0;
+}
+
 void default_reference(lbm_state *h)
 {
     std::memset(h->Q0, 0, sizeof h->Q0);
@@ -125,6 +139,7 @@ void default_reference(lbm_state *h)
     case SYS_NSE: h->Q0[0] = 1.0; break;
     case SYS_CNSF2D: cnsf2d_default_reference(h); break;
     case SYS_MHD: mhd_default_reference(h); break;
+    case SYS_HCNSF: hcnsf_default_reference(h); break;
     case SYS_EULER: euler_default_reference(h); break;
     }
 }
@@ -132,7 +147,7 @@ void default_reference(lbm_state *h)
 bool has_trackers(int sys)
 {
     return sys == SYS_ADVDIFF || sys == SYS_NSF17 || sys == SYS_ALLENCAHN || sys == SYS_NSE || sys == SYS_CNSF2D ||
-           sys == SYS_MHD;
+           sys == SYS_MHD || sys == SYS_HCNSF;
 }
 
 size_t arith_bytes(const lbm_state *h) { return h->storage == LBM_F64 ? 8 : 4; }
@@ -259,6 +274,26 @@ int lbm_set_param(lbm_state *h, const char *name, double v)
         break;
     case SYS_RELHYDRO:
         break;
+    case SYS_HCNSF:
+        if (n == "gamma") {
+            if (!(v > 1)) return fail(h, LBM_EINVAL, "gamma must exceed 1");
+            h->gamma = v;
+            if (!h->q0_set) hcnsf_default_reference(h);
+            return LBM_OK;
+        }
+        if (n == "mu") { h->mu = v; return LBM_OK; }
+        if (n == "kappa") { h->kappa = v; return LBM_OK; }
+        if (n == "eta") {
+            if (!(v > 0)) return fail(h, LBM_EINVAL, "eta must be positive");
+            h->eta_drag = v;
+            return LBM_OK;
+        }
+        if (n == "g_tau") {
+            if (!(v > 0)) return fail(h, LBM_EINVAL, "g_tau must be positive");
+            h->g_tau = v;
+            return LBM_OK;
+        }
+        break;
     case SYS_MHD:
         if (n == "gamma") {
             if (!(v > 1)) return fail(h, LBM_EINVAL, "gamma must exceed 1");
@@ -376,10 +411,12 @@ int lbm_set_reference(lbm_state *h, const double *Q0)
 {
     if (!h || !Q0) return LBM_EINVAL;
     if (h->bound) return fail(h, LBM_EINVAL, "reference is fixed once bound");
-    for (int k = 0; k < h->K; ++k) {
+    for (int k = 0; k < h->K; ++k)
         if (!std::isfinite(Q0[k])) return fail(h, LBM_EINVAL, "reference state is not finite");
-        h->Q0[k] = Q0[k];
-    }
+    if (h->sys == SYS_HCNSF)
+        for (int k = 5; k < h->K; ++k)
+            if (Q0[k] != 0.0) return fail(h, LBM_EINVAL, "hcnsf3d_trk14: the reference trackers must be zero");
+    for (int k = 0; k < h->K; ++k) h->Q0[k] = Q0[k];
     h->q0_set = true;
     return LBM_OK;
 }
@@ -443,6 +480,11 @@ int lbm_set_field(lbm_state *h, const char *name, const void *dev_ptr)
 {
     if (!h || !name) return LBM_EINVAL;
     if (h->sys == SYS_SWE && !std::strcmp(name, "grad_zb")) {
+        h->field_b = dev_ptr;
+        return LBM_OK;
+    }
+    if (h->sys == SYS_HCNSF && !std::strcmp(name, "coef")) {
+        if (h->storage == LBM_F16NE) return fail(h, LBM_EINVAL, "no coefficient field with F16NE storage");
         h->field_b = dev_ptr;
         return LBM_OK;
     }

@@ -213,8 +213,21 @@ __global__ __launch_bounds__(step_block<Sys>()) void k_step(const St *__restrict
     // deviation at the compensated moments: dPhi(hi) and, from one
     // forward-mode tangent, its first-order correction J(hi) lo.
     constexpr bool PRECISE = Sys::precise && !std::is_same<St, _Float16>::value;
+    // per-cell coefficient field (default values when none is attached)
+    using CT = CoefTraits<Sys>;
+    constexpr int NB = CT::NB;
+    R bl[NB > 3 ? NB : 3];
+#pragma unroll
+    for (int a = 0; a < (NB > 3 ? NB : 3); ++a) bl[a] = R(CT::dflt(a));
+    if (p.b) {
+#pragma unroll
+        for (int a = 0; a < NB; ++a) bl[a] = *byte_at(p.b + a * (size_t)p.C, cell * (I)sizeof(R));
+    }
     R dPhi[K][D], dPhiLo[K][D];
-    if constexpr (PRECISE) {
+    static_assert(!(PRECISE && CT::in_flux), "coefficient-dependent fluxes use the plain equilibrium");
+    if constexpr (CT::in_flux) {
+        Sys::template flux_delta_b<R, R>(p.phys, dQ, bl, dPhi);
+    } else if constexpr (PRECISE) {
         using D1 = Dual<R, 1>;
         D1 q1[K], P1[K][D];
 #pragma unroll
@@ -234,11 +247,6 @@ __global__ __launch_bounds__(step_block<Sys>()) void k_step(const St *__restrict
         Sys::template flux_delta<R, R>(p.phys, dQ, dPhi);
     }
     R Sk[K];
-    R bl[3] = {R(0), R(0), R(0)};       // per-cell source field (zero when none is attached)
-    if (p.b) {
-#pragma unroll
-        for (int a = 0; a < D; ++a) bl[a] = *byte_at(p.b + a * (size_t)p.C, cell * (I)sizeof(R));
-    }
     Sys::template source<R, R>(p.phys, dQ, bl, Sk);
     if constexpr (Sys::id == SYS_NSF17) {
         if (p.mms.on) {
@@ -316,9 +324,28 @@ __global__ __launch_bounds__(step_block<Sys>()) void k_step(const St *__restrict
 // ------------------------------------------------------------- init ----
 // Shifted equilibrium of the given fields, in double, written in the pull
 // layout: the population i of cell x lives at x - c_i.
+// Flux deviation at double precision for the initialisation kernels; a
+// system whose flux reads the coefficient field takes the cell's values
+// (coef: [NB][C] in the stepping arithmetic type, or null for defaults).
+template <class Sys, int D, class BT>
+__device__ inline void init_flux_delta(const Phys<double> &ph, const double *dQ, const BT *coef, size_t C,
+                                       long long cell, double dPhi[][D])
+{
+    using CT = CoefTraits<Sys>;
+    if constexpr (CT::in_flux) {
+        double bl[CT::NB];
+#pragma unroll
+        for (int a = 0; a < CT::NB; ++a) bl[a] = coef ? (double)coef[(size_t)a * C + cell] : CT::dflt(a);
+        Sys::template flux_delta_b<double, double>(ph, dQ, bl, dPhi);
+    } else {
+        Sys::template flux_delta<double, double>(ph, dQ, dPhi);
+    }
+}
+
 template <class Sys, class Lat, class St>
 __global__ __launch_bounds__(kBlock) void k_init(const double *__restrict__ Qin, St *__restrict__ fout,
-                                                 const KParams<double> p)
+                                                 const KParams<double> p,
+                                                 const typename Store<St>::R *__restrict__ coef)
 {
     constexpr int K = Sys::K, Q = Lat::Q, D = Lat::D;
     const long long cell = (long long)blockIdx.x * kBlock + threadIdx.x;
@@ -331,7 +358,7 @@ __global__ __launch_bounds__(kBlock) void k_init(const double *__restrict__ Qin,
     double dQ[K], dPhi[K][D];
 #pragma unroll
     for (int k = 0; k < K; ++k) dQ[k] = Qin[(size_t)k * C + cell] - p.phys.Q0[k];
-    Sys::template flux_delta<double, double>(p.phys, dQ, dPhi);
+    init_flux_delta<Sys, D>(p.phys, dQ, coef, C, cell, dPhi);
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
@@ -345,9 +372,9 @@ __global__ __launch_bounds__(kBlock) void k_init(const double *__restrict__ Qin,
 }
 
 // per-block maxima of |f*eq_{k,i}| per field (chooses the F16 scales)
-template <class Sys, class Lat>
+template <class Sys, class Lat, class BT>
 __global__ __launch_bounds__(kBlock) void k_init_absmax(const double *__restrict__ Qin, double *__restrict__ part,
-                                                        const KParams<double> p)
+                                                        const KParams<double> p, const BT *__restrict__ coef)
 {
     constexpr int K = Sys::K, Q = Lat::Q, D = Lat::D;
     __shared__ double sh[kBlock / 64];
@@ -360,7 +387,7 @@ __global__ __launch_bounds__(kBlock) void k_init_absmax(const double *__restrict
         double dQ[K], dPhi[K][D];
 #pragma unroll
         for (int k = 0; k < K; ++k) dQ[k] = Qin[(size_t)k * C + cell] - p.phys.Q0[k];
-        Sys::template flux_delta<double, double>(p.phys, dQ, dPhi);
+        init_flux_delta<Sys, D>(p.phys, dQ, coef, C, cell, dPhi);
 #pragma unroll
         for (int k = 0; k < K; ++k)
 #pragma unroll
@@ -687,13 +714,15 @@ struct Impl {
     static hipError_t init(const lbm_state_impl &h, const double *Q, void *fout, hipStream_t s)
     {
         const KParams<double> p = h.kparams<double>(h.t0);
-        hipLaunchKernelGGL((k_init<Sys, Lat, St>), dim3(grid(h.C)), dim3(kBlock), 0, s, Q, (St *)fout, p);
+        hipLaunchKernelGGL((k_init<Sys, Lat, St>), dim3(grid(h.C)), dim3(kBlock), 0, s, Q, (St *)fout, p,
+                           (const R *)h.field_b);
         return hipGetLastError();
     }
     static hipError_t init_absmax(const lbm_state_impl &h, const double *Q, double *part, hipStream_t s)
     {
         const KParams<double> p = h.kparams<double>(h.t0);
-        hipLaunchKernelGGL((k_init_absmax<Sys, Lat>), dim3(kRedBlocks), dim3(kBlock), 0, s, Q, part, p);
+        hipLaunchKernelGGL((k_init_absmax<Sys, Lat, R>), dim3(kRedBlocks), dim3(kBlock), 0, s, Q, part, p,
+                           (const R *)h.field_b);
         return hipGetLastError();
     }
     static hipError_t moments(const lbm_state_impl &h, const void *fin, void *out, int absolute, int out_dtype,

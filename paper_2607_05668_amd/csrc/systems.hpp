@@ -14,6 +14,8 @@
 
 #include "dual.hpp"
 
+#include <type_traits>
+
 #define LBM_MAXK 18
 
 // Per-run constants shared by all systems (filled on the host in double and
@@ -35,6 +37,7 @@ struct Phys {
     R cs2_phys;           // weakly compressible NSE: artificial sound speed squared
     R sq_ref;             // ultrarelativistic: sqrt(4 E0^2 - 3 |S0|^2)
     R inv_R_gas;          // 2D compressible NSF: 1 / R (T = p / (R rho))
+    R inv_eta;            // homogenized NSF: drag rate 1 / eta
     R H0[4];              // F0 - I (reference deformation minus identity)
     R P0[4];              // first Piola-Kirchhoff stress at F0
 };
@@ -837,4 +840,136 @@ struct SysNSF17 {
         const R c2 = p.gamma * pr / rho;
         return sqrt(u0 * u0 + u1 * u1 + u2 * u2) + sqrt(c2 > R(0) ? c2 : R(0));
     }
+};
+
+// ---------------------------------------------------------------- HCNSF --
+// Homogenized compressible NSF in 3D (Sec. 3, homogenized NSF) with the
+// strain-reduced tracker basis: Q = (rho, rho u, E, G_u, G_T) with
+// G_u = sym grad u stored as (00, 11, 22, 01, 02, 12) and G_T = grad T,
+// T = p / rho, 14 fields.  Prescribed per-cell coefficients (alpha, u_s):
+// porosity alpha scales the viscous stress and the heat flux, and the drag
+// (1 - alpha) / eta (rho u_s - rho u) forces momentum and energy.
+//   Phi_m  = m u^T + p I - alpha tau,  tau = mu (2 G_u - 2/3 tr(G_u) I)
+//   Phi_E  = (E + p) u - alpha tau u - alpha kappa G_T
+//   Phi_Gu = G_u u^T - sym(I (x) u) / tau_grad,  Phi_GT = G_T u^T - T I / tau_grad
+// The reference trackers are zero (the library enforces it), so the
+// reference flux does not depend on alpha and the deviation of the
+// dissipative terms is the terms themselves.
+struct SysHCNSF {
+    static constexpr int K = 14, D = 3, id = 12;
+    static constexpr bool precise = false;
+    static constexpr bool compensated = true;
+    static constexpr bool tracker(int k) { return k >= 5; }
+    // coefficient field: 4 values per cell, read by the flux as well
+    static constexpr int NB = 4;
+    static constexpr bool coef_in_flux = true;
+    __host__ __device__ static constexpr double coef_default(int a) { return a == 0 ? 1.0 : 0.0; }
+
+    template <class S, class R>
+    __host__ __device__ static void flux_delta_b(const Phys<R> &p, const S *dQ, const R *b, S dPhi[][D])
+    {
+        const S drho = dQ[0];
+        const S rho = drho + p.Q0[0];
+        const S irho = R(1) / rho;
+        S u[3], du[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            du[a] = (dQ[1 + a] - drho * p.u_ref[a]) * irho;
+            u[a] = du[a] + p.u_ref[a];
+        }
+        const S dk = (rho * (du[0] * (du[0] + R(2) * p.u_ref[0]) + du[1] * (du[1] + R(2) * p.u_ref[1])
+                             + du[2] * (du[2] + R(2) * p.u_ref[2]))
+                      + drho * (p.u_ref[0] * p.u_ref[0] + p.u_ref[1] * p.u_ref[1] + p.u_ref[2] * p.u_ref[2]))
+                     * R(0.5);
+        const S dp = (dQ[4] - dk) * (p.gamma - R(1));
+        const S dT = (dp - drho * p.T_ref) * irho;
+        // alpha tau from the strain trackers (symmetric)
+        const R amu = b[0] * p.mu, akappa = b[0] * p.kappa;
+        const S tr3 = (dQ[5] + dQ[6] + dQ[7]) * R(2.0 / 3.0);
+        S at[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) at[a][a] = (R(2) * dQ[5 + a] - tr3) * amu;
+        at[0][1] = at[1][0] = R(2) * dQ[8] * amu;
+        at[0][2] = at[2][0] = R(2) * dQ[9] * amu;
+        at[1][2] = at[2][1] = R(2) * dQ[10] * amu;
+        const S dH = dQ[4] + dp;                          // d(E + p)
+        const R half_itg = R(0.5) * p.inv_tau_grad;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            dPhi[0][c] = dQ[1 + c];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                S v = dQ[1 + a] * u[c] + du[c] * p.Q0[1 + a] - at[a][c];
+                if (a == c) v = v + dp;
+                dPhi[1 + a][c] = v;
+            }
+            dPhi[4][c] = dH * u[c] + du[c] * p.H_ref - (at[c][0] * u[0] + at[c][1] * u[1] + at[c][2] * u[2])
+                         - dQ[11 + c] * akappa;
+            // diagonal strain trackers: - delta_ac du_a / tau_grad
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                S v = dQ[5 + a] * u[c];
+                if (a == c) v = v - du[a] * p.inv_tau_grad;
+                dPhi[5 + a][c] = v;
+            }
+            // off-diagonal (01, 02, 12): - (delta_bc du_a + delta_ac du_b) / (2 tau_grad)
+            {
+                S v01 = dQ[8] * u[c], v02 = dQ[9] * u[c], v12 = dQ[10] * u[c];
+                if (c == 0) { v01 = v01 - du[1] * half_itg; v02 = v02 - du[2] * half_itg; }
+                if (c == 1) { v01 = v01 - du[0] * half_itg; v12 = v12 - du[2] * half_itg; }
+                if (c == 2) { v02 = v02 - du[0] * half_itg; v12 = v12 - du[1] * half_itg; }
+                dPhi[8][c] = v01;
+                dPhi[9][c] = v02;
+                dPhi[10][c] = v12;
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                S v = dQ[11 + a] * u[c];
+                if (a == c) v = v - dT * p.inv_tau_grad;
+                dPhi[11 + a][c] = v;
+            }
+        }
+    }
+
+    template <class S, class R>
+    __host__ __device__ static void source(const Phys<R> &p, const S *dQ, const R *b, S *Sk)
+    {
+        const S rho = dQ[0] + p.Q0[0];
+        const R drag = (R(1) - b[0]) * p.inv_eta;
+        Sk[0] = S(R(0));
+        S se = S(R(0));
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const S m = dQ[1 + a] + p.Q0[1 + a];
+            const S sm = (rho * b[1 + a] - m) * drag;
+            Sk[1 + a] = sm;
+            se = se + sm * (m / rho);
+        }
+        Sk[4] = se;
+#pragma unroll
+        for (int k = 5; k < K; ++k) Sk[k] = (dQ[k] + p.Q0[k]) * (-p.inv_tau_grad);
+    }
+
+    template <class R>
+    __host__ __device__ static R max_speed(const Phys<R> &p, const R *Q)
+    {
+        return SysNSF17::max_speed(p, Q);
+    }
+};
+
+// Per-cell coefficient field of a system: NB values per cell ([NB][cells]),
+// read by the source and, where coef_in_flux, by the flux; missing values
+// take coef_default.  Systems without these members read D values (the
+// topography gradient of SWE), zero when no field is attached.
+template <class S, class = void>
+struct CoefTraits {
+    static constexpr int NB = S::D;
+    static constexpr bool in_flux = false;
+    __host__ __device__ static constexpr double dflt(int) { return 0.0; }
+};
+template <class S>
+struct CoefTraits<S, std::void_t<decltype(S::NB)>> {
+    static constexpr int NB = S::NB;
+    static constexpr bool in_flux = S::coef_in_flux;
+    __host__ __device__ static constexpr double dflt(int a) { return S::coef_default(a); }
 };

@@ -414,3 +414,50 @@ def nsf_exact(n: int, t: float, mms: NsfMms = NsfMms()):
         dp = c2 * drho[b] + dpi[b]
         out[14 + b] = (dp - T * drho[b]) / rho
     return out
+
+
+# --------------------------------------------------------------------------
+# 3D homogenized NSF (14 fields): the paper's MMS working point (Ma 0.5,
+# amplitude 0.2, rho0 = cs = 1 with isothermal cs, p0 = 1), SI transport
+# coefficients (mu = kappa = 3.52 Pa s, eta = 0.348 ms at rho0 = 1.225,
+# cs = 287.4) read in those units; single-precision recipe.
+# --------------------------------------------------------------------------
+HCNSF_MMS = NsfMms(mach=0.5, amp=0.2)
+PRESETS["hcnsf256"] = Preset("hcnsf256", "hcnsf3d_trk14", "D3Q7", 256, "f32", 100,
+                             "acoustic", 0.05, 20.0, 3.0,
+                             {"gamma": 1.4, "mu": 3.52 / (1.225 * 287.4), "kappa": 3.52 / (1.225 * 287.4),
+                              "eta": 0.000348 * 287.4})
+
+
+def hcnsf_exact(n: int, t: float):
+    """Exact fields [14, n, n, n] of the homogenized-NSF MMS at time t:
+    rho, rho u (3), E, sym grad u as (00, 11, 22, 01, 02, 12), grad T."""
+    q = nsf_exact(n, t, HCNSF_MMS)
+    out = np.zeros((14, n, n, n))
+    out[:5] = q[:5]
+    for s, (a, b) in enumerate(((0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2))):
+        out[5 + s] = 0.5 * (q[5 + 3 * a + b] + q[5 + 3 * b + a])
+    out[11:14] = q[14:17]
+    return out
+
+
+def hcnsf_coefficients(n: int, t: float):
+    """Prescribed (alpha, u_s) [4, n, n, n] of the homogenized-NSF MMS at time
+    t: solid velocity = rotation (0.2) + translation (0.1, -0.1, 0.05) +
+    oscillation (0.1); porosity 1/2 + [sin k xi_0 + sin k xi_1 + sin k xi_2 +
+    2 sin k xi_0 sin k xi_1 sin k xi_2] / 10 along xi = x - d,
+    d = r(x) sin t + c t (r: the rotation's spatial profile)."""
+    X, Y, Z = grid3(n)
+    k = 2.0 * math.pi
+    c = (0.1, -0.1, 0.05)
+    r = [0.2 * np.sin(k * X) * np.cos(k * Y) * np.cos(k * Z),
+         -0.2 * np.cos(k * X) * np.sin(k * Y) * np.cos(k * Z),
+         0.2 * np.cos(k * X) * np.cos(k * Y) * np.sin(k * Z)]
+    st, ct = math.sin(t), math.cos(t)
+    out = np.zeros((4, n, n, n))
+    out[1] = r[0] * ct + c[0] + 0.1 * st * np.cos(k * Z)
+    out[2] = r[1] * ct + c[1] + 0.1 * ct * np.cos(k * X)
+    out[3] = r[2] * st + c[2] + 0.1 * st * np.cos(k * Y)
+    s = [np.sin(k * (v - (r[i] * st + c[i] * t))) for i, v in enumerate((X, Y, Z))]
+    out[0] = 0.5 + (s[0] + s[1] + s[2] + 2.0 * s[0] * s[1] * s[2]) / 10.0
+    return out

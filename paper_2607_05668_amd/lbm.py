@@ -188,13 +188,20 @@ class Stepper:
     def set_param(self, name, value):
         self._check(self.lib.lbm_set_param(self.h, name.encode(), float(value)))
 
+    # values per cell of each named per-cell field
+    FIELD_COMPONENTS = {"grad_zb": 2, "coef": 4}
+
     def set_field(self, name, value):
-        """Attach a per-cell source field (e.g. "grad_zb", [D, ...]); keeps a reference."""
+        """Attach a per-cell field: "grad_zb" (swe2d, [2, ...]) or "coef"
+        (hcnsf3d_trk14: alpha, u_s, [4, ...]); keeps a reference."""
         if value is None:
             self._fields.pop(name, None)
             self._check(self.lib.lbm_set_field(self.h, name.encode(), None))
             return
         t = self.torch.as_tensor(value, device=self.device, dtype=self.real).contiguous()
+        nb = self.FIELD_COMPONENTS.get(name)
+        if nb is not None and t.numel() != nb * self.C:
+            raise ValueError(f"field {name!r} needs {nb} x {self.C} values, got {t.numel()}")
         self._fields[name] = t
         self._check(self.lib.lbm_set_field(self.h, name.encode(), t.data_ptr()))
 

@@ -78,3 +78,34 @@ def test_reference_rounds_to_float_for_single_precision_storage():
     lib.lbm_get_reference(h, out.ctypes.data_as(dp))
     assert np.all(out == np.float32(q0).astype(np.float64))
     lib.lbm_destroy(h)
+
+
+def test_hcnsf_reference_and_coefficient_field_validation():
+    """hcnsf3d_trk14: default reference is the Mach-0.5 background (trackers
+    zero); a reference with non-zero trackers is rejected (the flux's
+    reference value must not depend on the porosity); the coefficient field
+    is named "coef" and other systems do not take it."""
+    import math
+
+    import numpy as np
+    lib = lbm.load_library()
+    dp = ctypes.POINTER(ctypes.c_double)
+    h = ctypes.c_void_p(lib.lbm_create(b"hcnsf3d_trk14", b"D3Q7", 8, 8, 8, 0.6, 1e-3, 1e-2))
+    assert h.value and lib.lbm_num_fields(h) == 14
+    assert lib.lbm_set_storage(h, lbm.STORAGE["f64"]) == 0
+    q0 = np.zeros(14)
+    assert lib.lbm_get_reference(h, q0.ctypes.data_as(dp)) == 0
+    u0 = 0.5 * math.sqrt(1.4)
+    assert np.allclose(q0[:5], [1, u0, u0, u0, 2.5 + 1.5 * u0 * u0], rtol=1e-15) and not q0[5:].any()
+    bad = q0.copy()
+    bad[7] = 1e-3
+    assert lib.lbm_set_reference(h, bad.ctypes.data_as(dp)) == lbm.LBM_EINVAL
+    assert b"trackers" in lib.lbm_last_error(h)
+    assert lib.lbm_set_field(h, b"coef", None) == 0
+    assert lib.lbm_set_field(h, b"grad_zb", None) == lbm.LBM_EINVAL
+    assert lib.lbm_set_param(h, b"eta", 0.0) == lbm.LBM_EINVAL
+    lib.lbm_destroy(h)
+    h = ctypes.c_void_p(lib.lbm_create(b"swe2d", b"D2Q9", 8, 8, 1, 0.6, 1e-3, 1e-2))
+    assert lib.lbm_set_field(h, b"coef", None) == lbm.LBM_EINVAL
+    lib.lbm_destroy(h)
+    assert not lib.lbm_create(b"hcnsf3d_trk14", b"D2Q5", 8, 8, 1, 0.6, 1e-3, 1e-2)

@@ -1,0 +1,97 @@
+"""GPU parity for the 3D homogenized compressible NSF system (14 fields:
+strain-reduced velocity-gradient trackers and temperature-gradient trackers,
+prescribed porosity and solid velocity per cell) against the FP64 oracle on
+the same inputs, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2607_05668_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2607_05668_amd import lbm  # noqa: E402
+
+GROUPS = {"rho": slice(0, 1), "m": slice(1, 4), "E": slice(4, 5), "G_u": slice(5, 11), "G_T": slice(11, 14)}
+PHYS = ("gamma", "mu", "kappa", "eta")
+
+
+def rel(a, b):
+    return math.sqrt(float(np.sum((a - b) ** 2)) / float(np.sum(b ** 2)))
+
+
+def make_pair(shape, storage, Q, B, tau_r):
+    pre = inputs.PRESETS["hcnsf256"]
+    n = max(shape)
+    dx = 1.0 / n
+    dt = pre.f * dx
+    g = lbm.Stepper("hcnsf3d_trk14", "D3Q7", shape, 0.5 + tau_r * dt, dt, dx, storage,
+                    dict(pre.params, g_tau=pre.g_tau))
+    if B is not None:
+        g.set_field("coef", B)
+    g.init(Q)
+    o = oracle.Oracle("hcnsf3d_trk14", "D3Q7", shape, g.param("dt"), g.param("dx"), 1.0 / g.param("omega"),
+                      g.param("g_tau"), {k: pre.params[k] for k in PHYS}, Q0=g.reference,
+                      omega_tracker=g.param("omega_tracker"))
+    # the oracle gets the coefficient values the kernels read (the field is
+    # held in the stepping arithmetic type)
+    Bo = None if B is None else np.asarray(g._fields["coef"].cpu().numpy(), dtype=np.float64).reshape(B.shape)
+    o.init(Q, b=Bo)
+    return g, o, Bo
+
+
+def advance(g, o, Bo, steps):
+    g.step(steps)
+    o.step(steps, b=Bo)
+    Qg, Qo = g.moments().cpu().numpy(), o.moments()
+    errs = {k: rel(Qg[s], Qo[s]) for k, s in GROUPS.items()}
+    print(f"step {g.steps}: rel L2 vs oracle", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    return errs
+
+
+@pytest.mark.parametrize("storage,n,tol,coef", [("f32", 24, 1e-6, True), ("f32", 24, 1e-6, False),
+                                                ("f64", 16, 1e-12, True)])
+def test_hcnsf_with_porosity_matches_oracle(storage, n, tol, coef):
+    """The paper's MMS state and coefficient fields at t = 0.4 (alpha over
+    [0.1, 0.9], moving solid), held fixed, without forcing; and the same
+    state as pure fluid (no coefficient field).  60 steps to every field's
+    tolerance; continued to 150 steps, the drag has pulled the momentum of
+    the solid region towards the solid velocity, 45% (RMS) away from the
+    reference state, and single-precision storage of the shifted
+    populations loses accuracy in proportion (measured: conserved fields
+    2.2e-7, trackers 1.4e-6): conserved fields are held to 1e-6 there and
+    trackers to 2e-6."""
+    print(f"hcnsf3d_trk14 D3Q7 {storage} {n}^3, coefficient field {coef}", flush=True)
+    Q = inputs.hcnsf_exact(n, 0.4)
+    B = inputs.hcnsf_coefficients(n, 0.4) if coef else None
+    g, o, Bo = make_pair((n, n, n), storage, Q, B, 20.0 if storage == "f32" else 10.0)
+    errs = advance(g, o, Bo, 60)
+    for k, v in errs.items():
+        assert v <= tol, k
+    errs = advance(g, o, Bo, 90)
+    for k, v in errs.items():
+        assert v <= (2 * tol if k.startswith("G_") else tol), k
+
+
+def test_hcnsf_ragged_grid_pure_fluid():
+    """7 x 13 x 40 cells (ragged tiles), no coefficient field (alpha = 1)."""
+    print("hcnsf3d_trk14 D3Q7 f32 40x13x7 100 steps, no coefficient field", flush=True)
+    shape = (7, 13, 40)
+    z, y, x = np.meshgrid(np.arange(7) / 7, np.arange(13) / 13, np.arange(40) / 40, indexing="ij")
+    u0 = 0.5 * math.sqrt(1.4)
+    Q = np.zeros((14,) + shape)
+    Q[0] = 1.0 + 0.05 * np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y) * np.sin(2 * np.pi * z)
+    for a in range(3):
+        Q[1 + a] = u0 + 0.03 * np.cos(2 * np.pi * (x + a * y - z))
+    Q[4] = 2.5 + 1.5 * u0 * u0 + 0.04 * np.cos(2 * np.pi * (x - z))
+    Q[5:] = 0.1 * np.sin(2 * np.pi * (x + 2 * y + 3 * z))[None]
+    g, o, Bo = make_pair(shape, "f32", Q, None, 20.0)
+    errs = advance(g, o, Bo, 100)
+    for k, v in errs.items():
+        assert v <= 1e-6, k

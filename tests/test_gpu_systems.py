@@ -191,7 +191,8 @@ MHD_ETA = 3.4 / 340.0
 
 
 @pytest.mark.parametrize("lattice,shape,storage,tol", [
-    ("D2Q5", (64, 64), "f32", 1e-6), ("D2Q5", (40, 56), "f32", 1e-6), ("D2Q5", (48, 48), "f64", 1e-12)])
+    ("D2Q5", (64, 64), "f32", 1e-6), ("D2Q5", (40, 56), "f32", 1e-6), ("D2Q9", (40, 64), "f32", 1e-6),
+    ("D2Q5", (48, 48), "f64", 1e-12)])
 def test_mhd_matches_oracle(lattice, shape, storage, tol):
     """The paper's resistive MHD state at t = 0 (Mach 3 per axis, B = 0.5 cs
     per axis, exact conserved-field trackers; mu = K = eta = 0.01 read with
