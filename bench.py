@@ -213,6 +213,59 @@ def extra_runs(torch, lbm, inputs):
     return out
 
 
+# The paper's roofline table, row for row: every system on its lattice
+# (D2Q5 in 2D, D3Q7 for the homogenized NSF) in single and double
+# precision, on a saturating grid (2048^2, 256^3), with the paper's
+# single-precision recipes.  Bytes per cell update: 2 K Q sizeof (+ the
+# porosity / solid-velocity field the homogenized NSF reads).
+TABLE_ROWS = [
+    # (row, preset, initial-state function, extra values per cell)
+    ("Inviscid Burgers", "burgers2048", "burgers_initial", 0),
+    ("Compressible Euler", "euler2048", "euler_initial", 0),
+    ("Shallow Water (SWE)", "swe1024", "swe_initial", 0),
+    ("Ideal Ultrarelativistic Fluid", "relhydro2048", "relhydro_initial", 0),
+    ("Maxwell (TM)", "maxwell2048", "maxwell_initial", 0),
+    ("Nonlinear Elasticity", "neohooke2048", "neohooke_initial", 0),
+    ("Scalar ADR", "advdiff64", "advdiff_initial", 0),
+    ("Allen-Cahn Phase-Field", "allencahn2048", "allencahn_initial", 0),
+    ("Incompressible NSE", "nse2048", "nse_initial", 0),
+    ("Compressible NSF", "cnsf2048", "cnsf2d_initial", 0),
+    ("Resistive MHD", "mhd2048", "mhd_initial", 0),
+    ("HCNSF", "hcnsf256", "hcnsf_exact", 4),
+]
+
+
+def roofline_table(torch, lbm, inputs, steps):
+    copy_peak = probe_peak(torch, lbm)
+    rows = []
+    for row, pre_name, init_name, extra in TABLE_ROWS:
+        pre = inputs.PRESETS[pre_name]
+        three_d = pre.lattice == "D3Q7"
+        n = 256 if three_d else 2048
+        lat = "D3Q7" if three_d else "D2Q5"
+        init = getattr(inputs, init_name)
+        Q = init(n, 0.0) if init_name == "hcnsf_exact" else init(n)
+        for storage, size in (("f32", 4), ("f64", 8)):
+            g = lbm.from_preset(pre, n=n, storage=storage, lattice=lat)
+            if extra:
+                g.set_field("coef", inputs.hcnsf_coefficients(n, 0.0))
+            g.init(Q)
+            g.step(5)
+            _, kern = time_steps(torch, g, steps, per_launch=False)
+            bpc = (2 * g.K * g.Q + extra) * size
+            gbps = bpc * g.C / kern / 1e6
+            rows.append({"system": row, "lattice": lat, "fields": g.K, "precision": storage, "cells": g.C,
+                         "byte_per_cell": bpc, "mlups": round(g.C / kern / 1e3, 1),
+                         "mlups_x_vars": round(g.C * g.K / kern / 1e3, 1), "ms_per_step": round(kern, 5),
+                         "GBps": round(gbps, 1), "frac_of_8TBps": round(gbps / HBM_PEAK_GBPS, 4),
+                         "frac_of_copy_probe": round(gbps / copy_peak, 4)})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+            del g
+            torch.cuda.empty_cache()
+    return {"table": "all systems, paper's lattices, FP32 and FP64", "copy_probe_GBps": copy_peak,
+            "steps": steps, "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,6 +274,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the adjoint ratio, probe and extra workloads")
     ap.add_argument("--counters", action="store_true", help="short run for rocprofv3 counter collection")
+    ap.add_argument("--table", action="store_true",
+                    help="instead of the benchmark: every system in FP32 and FP64 on the paper's lattices")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this library has no multi-GPU path "
@@ -230,6 +285,9 @@ def main():
     import torch
     from paper_2607_05668_amd import inputs, lbm
 
+    if args.table:
+        print(json.dumps(roofline_table(torch, lbm, inputs, min(args.steps, 50))))
+        return
     p = inputs.PRESETS["swe1024"]
     g = lbm.from_preset(p)
     g.init(inputs.swe_initial(p.n))

@@ -143,18 +143,25 @@ __device__ inline void nsf_mms_source(const MmsParams<R> &m, const Phys<R> &p, R
 // values live per cell: a 512-thread workgroup (two waves per SIMD) caps a
 // wave at 256 of the SIMD's 512 registers per lane, so two waves share each
 // SIMD and one hides the other's loads (in FP32 it needs 230, no spills).
-template <class Sys>
-constexpr int step_block() { return Sys::K > 6 ? 512 : kBlock; }
+// In FP64 the largest states (more than 12 fields) need more than 256 even
+// so and would spill to scratch; a 256-thread workgroup lets one wave per
+// SIMD keep the overflow in accumulation registers instead (resistive MHD
+// 1.77 -> 1.16 ms, homogenized NSF 6.07 -> 5.19 ms per step).
+template <class Sys, class St>
+constexpr int step_block()
+{
+    return (sizeof(St) == 8 && Sys::K > 12) ? kBlock : (Sys::K > 6 ? 512 : kBlock);
+}
 
 template <class Sys, class Lat, class St, bool REC, bool NT, bool O32>
-__global__ __launch_bounds__(step_block<Sys>()) void k_step(const St *__restrict__ fin, St *__restrict__ fout,
+__global__ __launch_bounds__((step_block<Sys, St>())) void k_step(const St *__restrict__ fin, St *__restrict__ fout,
                                                             const KParams<typename Store<St>::R> p,
                                                             typename Store<St>::R *__restrict__ qhist)
 {
     using R = typename Store<St>::R;
     using I = typename Index<O32>::T;
     constexpr int K = Sys::K, Q = Lat::Q, D = Lat::D;
-    constexpr int B = step_block<Sys>();
+    constexpr int B = step_block<Sys, St>();
     constexpr I S = sizeof(St);
     // Tiles never straddle two z-planes: tile t covers the in-plane indices
     // [tp B, tp B + B) of plane z = t / tpp (tpp tiles per plane), so z and
@@ -678,7 +685,7 @@ struct Impl {
     static void launch_step(const lbm_state_impl &h, const void *fin, void *fout, void *qhist, hipStream_t s,
                             const KParams<R> &p)
     {
-        constexpr int B = step_block<Sys>();
+        constexpr int B = step_block<Sys, St>();
         const long long tpp = ((long long)h.nx * h.ny + B - 1) / B;    // tiles per z-plane
         hipLaunchKernelGGL((k_step<Sys, Lat, St, REC, NT, O32>), dim3((unsigned)(tpp * h.nz)), dim3(B), 0, s,
                            (const St *)fin, (St *)fout, p, (R *)qhist);

@@ -279,7 +279,7 @@ class Stepper:
         return out
 
 
-def from_preset(preset, n=None, storage=None, params=None, reference=None, tau_r=None, f=None):
+def from_preset(preset, n=None, storage=None, params=None, reference=None, tau_r=None, f=None, lattice=None):
     """Stepper for a workload preset (paper_2607_05668_amd.inputs.PRESETS)."""
     n = preset.n if n is None else n
     dx, dt, tau = recipe(n, preset.scaling, preset.f if f is None else f,
@@ -289,7 +289,7 @@ def from_preset(preset, n=None, storage=None, params=None, reference=None, tau_r
     if preset.g_tau is not None:
         p["g_tau"] = preset.g_tau
     p.update(params or {})
-    return Stepper(preset.system, preset.lattice, (n,) * dim, tau, dt, dx, storage or preset.storage, p,
+    return Stepper(preset.system, lattice or preset.lattice, (n,) * dim, tau, dt, dx, storage or preset.storage, p,
                    reference=reference)
 
 
