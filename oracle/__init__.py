@@ -54,7 +54,8 @@ class _Cfg(ctypes.Structure):
                 ("shifted", ctypes.c_int),
                 ("lam", ctypes.c_double), ("dt", ctypes.c_double),
                 ("omega", ctypes.c_double * MAXK), ("Q0", ctypes.c_double * MAXK),
-                ("par", ctypes.c_double * 16)]
+                ("par", ctypes.c_double * 16),
+                ("trt", ctypes.c_int), ("omega_plus", ctypes.c_double * MAXK)]
 
 
 _lib = None
@@ -124,7 +125,8 @@ class Oracle:
     """
 
     def __init__(self, system, lattice, shape, dt, dx, tau, g_tau=None, params=None,
-                 Q0=None, shifted=True, omega_tracker=None):
+                 Q0=None, shifted=True, omega_tracker=None, trt_lambda=None, omega_plus=None,
+                 omega_plus_tracker=None):
         if LATTICE_DIM[lattice] != SYSTEM_DIM[system]:
             raise ValueError("lattice dimension does not match the system")
         self.lib = _load()
@@ -152,6 +154,14 @@ class Oracle:
             cfg.omega[k] = 1.0 / (g_tau + 1.0) if omega_tracker is None else omega_tracker
         for name, v in params.items():
             cfg.par[PARAM_INDEX[name]] = float(v)
+        # two-relaxation-time collision: the symmetric rate from the magic
+        # parameter, or given explicitly (conserved fields, trackers)
+        if trt_lambda is not None or omega_plus is not None:
+            cfg.trt = 1
+            trk = set(TRACKER_FIELDS.get(system, ()))
+            for k in range(MAXK):
+                given = omega_plus_tracker if k in trk else omega_plus
+                cfg.omega_plus[k] = given if given is not None else trt_omega_plus(cfg.omega[k], trt_lambda)
         if shifted:
             if Q0 is None:
                 raise ValueError("shifted form needs a reference state Q0")
@@ -231,6 +241,12 @@ class Oracle:
         out = np.zeros((self.K,) + self.shape)
         self.lib.oracle_init_adjoint(ctypes.byref(self.cfg), _ptr(lam0), _ptr(Qf), _ptr(out))
         return out
+
+
+def trt_omega_plus(omega_minus: float, magic: float) -> float:
+    """Symmetric TRT rate from the antisymmetric one and the magic parameter
+    Lambda = (1/omega+ - 1/2)(1/omega- - 1/2) (Ginzburg's TRT)."""
+    return 1.0 / (0.5 + magic / (1.0 / omega_minus - 0.5))
 
 
 def make(preset, n=None, shifted=True, Q0=None, params=None, tau_r=None, f=None):

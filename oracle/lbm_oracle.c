@@ -50,6 +50,9 @@ typedef struct {
     double omega[MAXK];   /* per-field collision rate                       */
     double Q0[MAXK];      /* reference state (zeros when unshifted)          */
     double par[16];       /* physical parameters, indices P_*                */
+    int trt;              /* 1: two-relaxation-time collision                */
+    double omega_plus[MAXK]; /* TRT: rate of the symmetric parts; omega[] then
+                                relaxes the antisymmetric parts              */
 } oracle_cfg;
 
 typedef struct {
@@ -57,6 +60,7 @@ typedef struct {
     int c[MAXQ][3];
     double w[MAXQ];
     double cs2;
+    int opp[MAXQ];        /* index of the opposite velocity -c_i            */
 } lattice;
 
 static lattice lattice_get(int id)
@@ -90,6 +94,9 @@ static lattice lattice_get(int id)
             L.w[i] = (i == 0) ? 1.0 / 4.0 : 1.0 / 8.0;
         }
     }
+    for (int i = 0; i < L.Q; ++i)
+        for (int j = 0; j < L.Q; ++j)
+            if (L.c[j][0] == -L.c[i][0] && L.c[j][1] == -L.c[i][1] && L.c[j][2] == -L.c[i][2]) L.opp[i] = j;
     return L;
 }
 
