@@ -168,8 +168,8 @@ def probe_pattern(torch, lbm, n, fields=3, reps=20):
 def extra_runs(torch, lbm, inputs):
     out = {}
 
-    def one(name, preset, n, storage, steps, bytes_per_cell, init, coef=None):
-        g = lbm.from_preset(preset, n=n, storage=storage)
+    def one(name, preset, n, storage, steps, bytes_per_cell, init, coef=None, params=None):
+        g = lbm.from_preset(preset, n=n, storage=storage, params=params)
         if coef is not None:
             g.set_field("coef", coef)
         g.init(init)
@@ -182,6 +182,9 @@ def extra_runs(torch, lbm, inputs):
 
     p = inputs.PRESETS["swe1024"]
     one("swe2d_D2Q9_f32_2048", p, 2048, "f32", 200, 216, inputs.swe_initial(2048))
+    # two-relaxation-time collision (magic parameter 3/16) on the same workload
+    one("swe2d_D2Q9_f32_2048_trt", p, 2048, "f32", 200, 216, inputs.swe_initial(2048),
+        params={"trt_lambda": 3.0 / 16.0})
     p = inputs.PRESETS["neohooke2048"]
     one("neohooke2d_D2Q9_f16_2048", p, 2048, "f16", 200, 216, inputs.neohooke_initial(2048))
     # binary16 non-equilibrium deviations + FP32 moments: 2 (K Q 2 + K 4) bytes

@@ -131,11 +131,24 @@ int lbm_num_velocities(const lbm_state *h);
  *   mhd_trk2d:      gamma, mu (dynamic viscosity), kappa (heat-flux coefficient
  *                   K, with T = p / rho), eta (magnetic diffusivity), g_tau
  *   hcnsf3d_trk14:  gamma, mu, kappa (T = p / rho), eta (drag time, > 0), g_tau
- *   all:            t0 (initial time) */
+ *   all:            t0 (initial time); trt_lambda (>= 0; 0 = BGK, the default):
+ *                   two-relaxation-time collision with this magic parameter
+ *                   Lambda = (1/omega+ - 1/2)(1/omega- - 1/2): the parts of
+ *                   each field's populations antisymmetric under c -> -c
+ *                   (which carry the flux) relax at the field's BGK rate
+ *                   omega-, the symmetric parts at omega+ (Sec. 2.4 names
+ *                   such operators as consuming the same equilibria).  Not
+ *                   with LBM_F16NE storage, the moment history or the
+ *                   adjoint (LBM_EINVAL). */
 int lbm_set_param(lbm_state *h, const char *name, double v);
 
 /* Read a parameter in use: "dt", "dx", "lambda" (dt/dx), "tau", "omega"
- * (conserved fields), "omega_tracker", "tau_grad", "g_tau", "g", "t0".
+ * (conserved fields), "omega_tracker", "tau_grad", "g_tau", "g", "t0",
+ * "trt_lambda", and once bound "omega_plus" / "omega_plus_tracker" (the
+ * symmetric TRT rates; equal to omega / omega_tracker under BGK).  Under TRT
+ * the kernels use a = (omega+ + omega-)/2 and b = (omega+ - omega-)/2, in
+ * single precision with 2 - a on the 2^-24 grid and b rounded once; omega
+ * and omega_plus then report a - b and a + b.
  * After lbm_bind with F32/F16 storage these are the values the kernels run
  * with: dt/dx is rounded once to float and 2 - omega to a multiple of 2^-24
  * (so that omega - 1 is exact in float), and dt, tau and the collision

@@ -50,6 +50,8 @@ struct KParams {
     R delta[LBM_MAXK];                // 2 - omega
     R c1[LBM_MAXK];                   // 1 - delta = omega - 1 (exactly representable)
     R c2[LBM_MAXK];                   // 2 - delta = omega
+    R tb[LBM_MAXK];                   // two-relaxation-time: (omega+ - omega-) / 2 (c1 = a - 1, c2 = a,
+                                      // a = (omega+ + omega-) / 2); zero under BGK
     float scale[LBM_MAXK];            // storage = value * scale (F16 only)
     float inv_scale[LBM_MAXK];
     Phys<R> phys;
@@ -112,6 +114,8 @@ struct lbm_state_impl {
     double cs_phys = 1.0;
     double R_gas = 1.0;
     double eta_drag = 0.1;                 // homogenized NSF: drag time eta
+    double trt_lambda = 0.0;               // two-relaxation-time magic parameter (0: BGK)
+    double trt_a[2] = {0, 0}, trt_b[2] = {0, 0};   // TRT (a, b) of conserved fields, trackers
     int mms_on = 0;
     double mms_amp = 0.05, mms_rho0 = 1.0, mms_p0 = 1.0, mms_u0 = 0.0;
     double t0 = 0.0;

@@ -101,8 +101,16 @@ KParams<R> lbm_state_impl::kparams(double t_half) const
         const double om = trk ? omega_t : omega_c;
         p.omega[k] = (R)om;
         p.delta[k] = (R)(2.0 - om);
-        p.c1[k] = (R)(om - 1.0);
-        p.c2[k] = (R)om;
+        if (trt_lambda > 0) {
+            const double a = trt_a[trk ? 1 : 0], b = trt_b[trk ? 1 : 0];
+            p.c1[k] = (R)(a - 1.0);
+            p.c2[k] = (R)a;
+            p.tb[k] = (R)b;
+        } else {
+            p.c1[k] = (R)(om - 1.0);
+            p.c2[k] = (R)om;
+            p.tb[k] = R(0);
+        }
         p.scale[k] = std::ldexp(1.0f, scale_exp[k]);
         p.inv_scale[k] = std::ldexp(1.0f, -scale_exp[k]);
     }

@@ -34,6 +34,7 @@ struct D2Q5 {
     static constexpr int cx[Q] = {0, 1, 0, -1, 0};
     static constexpr int cy[Q] = {0, 0, 1, 0, -1};
     static constexpr int cz[Q] = {0, 0, 0, 0, 0};
+    static constexpr int opp[Q] = {0, 3, 4, 1, 2};       // index of -c_i
     static constexpr double w[Q] = {1.0 / 3, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
     static constexpr double cs2 = 1.0 / 3;
     static constexpr int id = 0;
@@ -47,6 +48,7 @@ struct D2Q9 {
     static constexpr int cx[Q] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
     static constexpr int cy[Q] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
     static constexpr int cz[Q] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    static constexpr int opp[Q] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
     static constexpr double w[Q] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
                                     1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
     static constexpr double cs2 = 1.0 / 3;
@@ -60,6 +62,7 @@ struct D3Q7 {
     static constexpr int cx[Q] = {0, 1, -1, 0, 0, 0, 0};
     static constexpr int cy[Q] = {0, 0, 0, 1, -1, 0, 0};
     static constexpr int cz[Q] = {0, 0, 0, 0, 0, 1, -1};
+    static constexpr int opp[Q] = {0, 2, 1, 4, 3, 6, 5};
     static constexpr double w[Q] = {1.0 / 4, 1.0 / 8, 1.0 / 8, 1.0 / 8, 1.0 / 8, 1.0 / 8, 1.0 / 8};
     static constexpr double cs2 = 1.0 / 4;
     static constexpr int id = 2;

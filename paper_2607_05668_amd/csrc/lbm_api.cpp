@@ -241,6 +241,12 @@ int lbm_set_param(lbm_state *h, const char *name, double v)
     if (!std::isfinite(v)) return fail(h, LBM_EINVAL, "parameter value is not finite");
     const std::string n(name);
     if (n == "t0") { h->t0 = v; return LBM_OK; }
+    if (n == "trt_lambda") {
+        if (h->bound) return fail(h, LBM_EINVAL, "parameters are fixed once bound");
+        if (!(v >= 0)) return fail(h, LBM_EINVAL, "trt_lambda must be >= 0 (0: BGK)");
+        h->trt_lambda = v;
+        return LBM_OK;
+    }
     if (n == "check_subchar") { h->check_subchar = v != 0.0; return LBM_OK; }
     if (h->bound && n != "mms") return fail(h, LBM_EINVAL, "parameters are fixed once bound");
     switch (h->sys) {
@@ -390,6 +396,12 @@ int lbm_get_param(const lbm_state *h, const char *name, double *v)
     else if (n == "tau") *v = h->tau;
     else if (n == "omega") *v = h->bound ? h->omega_c : 1.0 / h->tau;
     else if (n == "omega_tracker") *v = h->bound ? h->omega_t : (h->g_tau > 0 ? 1.0 / (h->g_tau + 1.0) : 0.0);
+    else if (n == "trt_lambda") *v = h->trt_lambda;
+    else if (n == "omega_plus" || n == "omega_plus_tracker") {
+        const int c = n == "omega_plus" ? 0 : 1;
+        if (!h->bound) return LBM_EINVAL;                  // defined once bound
+        *v = h->trt_lambda > 0 ? h->trt_a[c] + h->trt_b[c] : (c ? h->omega_t : h->omega_c);
+    }
     else if (n == "tau_grad") *v = h->g_tau > 0 ? h->g_tau * h->dt : 0.0;
     else if (n == "g_tau") *v = h->g_tau;
     else if (n == "g") *v = h->g;
@@ -465,6 +477,33 @@ int lbm_bind(lbm_state *h, void *pop_a, void *pop_b, void *aux, void *hip_stream
         // both exact in float (a change of tau - 1/2 below 1e-5 relative)
         h->omega_c = 2.0 - std::nearbyint((2.0 - h->omega_c) * 16777216.0) / 16777216.0;
         h->omega_t = 2.0 - std::nearbyint((2.0 - h->omega_t) * 16777216.0) / 16777216.0;
+        h->tau = 1.0 / h->omega_c;
+    }
+    if (h->trt_lambda > 0) {
+        if (h->storage == LBM_F16NE) return fail(h, LBM_EINVAL, "two-relaxation-time collision needs F64/F32/F16 storage");
+        // omega- is the BGK rate (the flux moment relaxes at it); omega+ from
+        // the magic parameter.  The kernels use a = (omega+ + omega-)/2 and
+        // b = (omega+ - omega-)/2; in single precision 2 - a sits on the 2^-24
+        // grid (a - 1 exact) and b is rounded once, and the rates in use are
+        // a -+ b.
+        double *om[2] = {&h->omega_c, &h->omega_t};
+        for (int c = 0; c < 2; ++c) {
+            const double wm = *om[c];
+            const double wp = 1.0 / (0.5 + h->trt_lambda / (1.0 / wm - 0.5));
+            double a = 0.5 * (wp + wm), b = 0.5 * (wp - wm);
+            if (h->storage != LBM_F64) {
+                a = 2.0 - std::nearbyint((2.0 - a) * 16777216.0) / 16777216.0;
+                b = (double)(float)b;
+            }
+            h->trt_a[c] = a;
+            h->trt_b[c] = b;
+            *om[c] = a - b;
+        }
+        if (!has_trackers(h->sys)) {
+            h->trt_a[1] = h->trt_a[0];
+            h->trt_b[1] = h->trt_b[0];
+            h->omega_t = h->omega_c;
+        }
         h->tau = 1.0 / h->omega_c;
     }
     h->pop[0] = pop_a;
@@ -557,6 +596,7 @@ int lbm_step_record(lbm_state *h, int n, void *Q_hist_dev)
 {
     if (h && !Q_hist_dev) return fail(h, LBM_EINVAL, "null history pointer");
     if (h && h->storage == LBM_F16NE) return fail(h, LBM_EINVAL, "no moment history with F16NE storage");
+    if (h && h->trt_lambda > 0) return fail(h, LBM_EINVAL, "the moment history and the adjoint are BGK only");
     return run_steps(h, n, Q_hist_dev);
 }
 
@@ -610,6 +650,7 @@ int lbm_adjoint_seed(lbm_state *h, const void *dLdQ_dev, void *lam_dev)
 {
     int rc = check_ready(h);
     if (rc) return rc;
+    if (h->trt_lambda > 0) return fail(h, LBM_EINVAL, "the adjoint is BGK only");
     if (!h->L->adj_seed) return fail(h, LBM_EINVAL, "no adjoint for this system");
     if (!dLdQ_dev || !lam_dev) return fail(h, LBM_EINVAL, "null pointer");
     const hipError_t e = h->L->adj_seed(*h, dLdQ_dev, lam_dev, h->stream);
@@ -620,6 +661,7 @@ int lbm_adjoint_step(lbm_state *h, int n, void *lam_a, void *lam_b, const void *
 {
     int rc = check_ready(h);
     if (rc) return rc;
+    if (h->trt_lambda > 0) return fail(h, LBM_EINVAL, "the adjoint is BGK only");
     if (!h->L->adj_step) return fail(h, LBM_EINVAL, "no adjoint for this system");
     if (n < 0 || !lam_a || !lam_b || lam_a == lam_b || (n > 0 && !Q_hist_dev)) return fail(h, LBM_EINVAL, "bad adjoint arguments");
     if (grad_field_dev && !h->field_b) return fail(h, LBM_EINVAL, "no source field attached");
@@ -640,6 +682,7 @@ int lbm_adjoint_to_initial(lbm_state *h, const void *lam0_dev, const double *Q_i
 {
     int rc = check_ready(h);
     if (rc) return rc;
+    if (h->trt_lambda > 0) return fail(h, LBM_EINVAL, "the adjoint is BGK only");
     if (!h->L->adj_init) return fail(h, LBM_EINVAL, "no adjoint for this system");
     if (!lam0_dev || !Q_init_dev || !dLdQ0_dev) return fail(h, LBM_EINVAL, "null pointer");
     const hipError_t e = h->L->adj_init(*h, lam0_dev, Q_init_dev, dLdQ0_dev, h->stream);

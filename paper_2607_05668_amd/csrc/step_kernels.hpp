@@ -153,7 +153,7 @@ constexpr int step_block()
     return (sizeof(St) == 8 && Sys::K > 12) ? kBlock : (Sys::K > 6 ? 512 : kBlock);
 }
 
-template <class Sys, class Lat, class St, bool REC, bool NT, bool O32>
+template <class Sys, class Lat, class St, bool REC, bool NT, bool O32, bool TRT>
 __global__ __launch_bounds__((step_block<Sys, St>())) void k_step(const St *__restrict__ fin, St *__restrict__ fout,
                                                             const KParams<typename Store<St>::R> p,
                                                             typename Store<St>::R *__restrict__ qhist)
@@ -268,6 +268,11 @@ __global__ __launch_bounds__((step_block<Sys, St>())) void k_step(const St *__re
     // host places 2 - omega on the 2^-24 grid): e - f is exact when f is
     // within a factor two of e, so the update rounds once.  In the precise
     // path e = e_hi + e_lo and post = e_hi + (c1 (e_hi - f) + omega e_lo).
+    // Two-relaxation-time (TRT): with d_i = e_i - f_i and ib the opposite
+    // velocity, relaxing the symmetric and antisymmetric parts at omega+ and
+    // omega- is post_i = f_i + a d_i + b d_ib, a = (omega+ + omega-)/2 (in c1
+    // = a - 1 and c2 = a), b = (omega+ - omega-)/2: the BGK update plus
+    // b d_ib.
     // The rest population closes the zeroth moment,
     // post_0 = f_0 + dt S + sum_{i>0} (f_i - post_i), an identity of the
     // update (the weights sum to one, the flux enters only odd moments)
@@ -300,14 +305,31 @@ __global__ __launch_bounds__((step_block<Sys, St>())) void k_step(const St *__re
         const R dts = p.dt * Sk[k];
         ExactEq<Lat>::zeroth(dts, s);
         R acc = dts;
+        R bd[Q];                         // TRT: b d_i
+        if constexpr (TRT) {
+            const R tb = p.tb[k];
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                if constexpr (PRECISE)
+                    bd[i] = tb * ((eh[i] - f[k][i]) + el[i]);
+                else
+                    bd[i] = tb * (eh[i] - f[k][i]);
+            }
+        }
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             const R fi = f[k][i];
             R post;
-            if constexpr (PRECISE)
+            if constexpr (TRT) {
+                if constexpr (PRECISE)
+                    post = eh[i] + (fma(c1, eh[i] - fi, fma(c2, el[i], bd[Lat::opp[i]])) + s[i]);
+                else
+                    post = fma(c1, eh[i] - fi, eh[i] + bd[Lat::opp[i]]) + s[i];
+            } else if constexpr (PRECISE) {
                 post = eh[i] + (fma(c1, eh[i] - fi, c2 * el[i]) + s[i]);
-            else
+            } else {
                 post = fma(c1, eh[i] - fi, eh[i]) + s[i];
+            }
             St *dst = byte_at(fout + ((size_t)z * K + k) * blk, (I)i * P * S + own);
             if constexpr (std::is_same<St, _Float16>::value) {
                 const _Float16 hv = (_Float16)(post * (R)p.scale[k]);
@@ -681,41 +703,48 @@ struct Impl {
     using R = typename Store<St>::R;
     static unsigned grid(long long C) { return (unsigned)((C + kBlock - 1) / kBlock); }
 
-    template <bool REC, bool NT, bool O32>
+    template <bool REC, bool NT, bool O32, bool TRT>
     static void launch_step(const lbm_state_impl &h, const void *fin, void *fout, void *qhist, hipStream_t s,
                             const KParams<R> &p)
     {
         constexpr int B = step_block<Sys, St>();
         const long long tpp = ((long long)h.nx * h.ny + B - 1) / B;    // tiles per z-plane
-        hipLaunchKernelGGL((k_step<Sys, Lat, St, REC, NT, O32>), dim3((unsigned)(tpp * h.nz)), dim3(B), 0, s,
+        hipLaunchKernelGGL((k_step<Sys, Lat, St, REC, NT, O32, TRT>), dim3((unsigned)(tpp * h.nz)), dim3(B), 0, s,
                            (const St *)fin, (St *)fout, p, (R *)qhist);
     }
-    template <bool REC, bool NT>
+    template <bool REC, bool NT, bool TRT>
     static void launch_step(const lbm_state_impl &h, const void *fin, void *fout, void *qhist, hipStream_t s,
                             const KParams<R> &p)
     {
         // the 32-bit form needs one (slab, field) block and the history and
         // source planes below 4 GiB
         if (fits_o32((long long)h.nx * h.ny, Lat::Q, sizeof(St)) && fits_o32(h.C, 1, sizeof(R)))
-            launch_step<REC, NT, true>(h, fin, fout, qhist, s, p);
+            launch_step<REC, NT, true, TRT>(h, fin, fout, qhist, s, p);
         else
-            launch_step<REC, NT, false>(h, fin, fout, qhist, s, p);
+            launch_step<REC, NT, false, TRT>(h, fin, fout, qhist, s, p);
     }
     static hipError_t step(const lbm_state_impl &h, const void *fin, void *fout, void *qhist, hipStream_t s)
     {
         const double t_half = h.t0 + (h.nsteps + 0.5) * h.dt;
         const KParams<R> p = h.kparams<R>(t_half);
         const bool nt = 2 * (size_t)Sys::K * Lat::Q * sizeof(St) * (size_t)h.C > kLastLevelCacheBytes;
+        const bool trt = h.trt_lambda > 0;
+        if (qhist && trt) return hipErrorInvalidValue;   // the moment history serves the BGK adjoint
         if constexpr (Sys::K <= 6) {
             if (qhist) {
-                nt ? launch_step<true, true>(h, fin, fout, qhist, s, p)
-                   : launch_step<true, false>(h, fin, fout, qhist, s, p);
+                nt ? launch_step<true, true, false>(h, fin, fout, qhist, s, p)
+                   : launch_step<true, false, false>(h, fin, fout, qhist, s, p);
                 return hipGetLastError();
             }
         } else {
             if (qhist) return hipErrorInvalidValue;   // no adjoint for the 3D cascade
         }
-        nt ? launch_step<false, true>(h, fin, fout, qhist, s, p) : launch_step<false, false>(h, fin, fout, qhist, s, p);
+        if (trt)
+            nt ? launch_step<false, true, true>(h, fin, fout, qhist, s, p)
+               : launch_step<false, false, true>(h, fin, fout, qhist, s, p);
+        else
+            nt ? launch_step<false, true, false>(h, fin, fout, qhist, s, p)
+               : launch_step<false, false, false>(h, fin, fout, qhist, s, p);
         return hipGetLastError();
     }
     static hipError_t init(const lbm_state_impl &h, const double *Q, void *fout, hipStream_t s)

@@ -109,3 +109,39 @@ def test_hcnsf_reference_and_coefficient_field_validation():
     assert lib.lbm_set_field(h, b"coef", None) == lbm.LBM_EINVAL
     lib.lbm_destroy(h)
     assert not lib.lbm_create(b"hcnsf3d_trk14", b"D2Q5", 8, 8, 1, 0.6, 1e-3, 1e-2)
+
+
+def test_trt_parameters_and_bgk_only_paths():
+    """trt_lambda: the rates in use after binding (omega- = the BGK rate,
+    omega+ from the magic parameter, single-precision rounding of
+    a = (omega+ + omega-)/2 and b = (omega+ - omega-)/2), rejection of the
+    moment history / adjoint and of F16NE storage.  Binding with stand-in
+    addresses touches no memory."""
+    import numpy as np
+    lib = lbm.load_library()
+    v = ctypes.c_double()
+    for storage, rtol in (("f64", 1e-15), ("f32", 1e-6)):
+        h = ctypes.c_void_p(lib.lbm_create(b"swe2d", b"D2Q9", 64, 64, 1, 0.6, 1e-3, 1e-2))
+        assert lib.lbm_set_param(h, b"trt_lambda", -1.0) == lbm.LBM_EINVAL
+        assert lib.lbm_set_param(h, b"trt_lambda", 0.1875) == 0
+        assert lib.lbm_set_storage(h, lbm.STORAGE[storage]) == 0
+        assert lib.lbm_get_param(h, b"omega_plus", ctypes.byref(v)) == lbm.LBM_EINVAL    # not bound yet
+        assert lib.lbm_bind(h, ctypes.c_void_p(256), ctypes.c_void_p(512), ctypes.c_void_p(768), None) == 0
+        lib.lbm_get_param(h, b"omega", ctypes.byref(v))
+        wm = v.value
+        lib.lbm_get_param(h, b"omega_plus", ctypes.byref(v))
+        wp = v.value
+        assert wm == pytest.approx(1 / 0.6, rel=rtol)
+        assert (1 / wp - 0.5) * (1 / wm - 0.5) == pytest.approx(0.1875, rel=10 * rtol)
+        if storage == "f32":
+            a, b = 0.5 * (wp + wm), 0.5 * (wp - wm)
+            assert np.float32(a) == a and np.float32(a - 1) == a - 1 and np.float32(b) == b
+        assert lib.lbm_step_record(h, 1, ctypes.c_void_p(1024)) == lbm.LBM_EINVAL
+        assert b"BGK" in lib.lbm_last_error(h)
+        assert lib.lbm_adjoint_seed(h, ctypes.c_void_p(1024), ctypes.c_void_p(2048)) == lbm.LBM_EINVAL
+        lib.lbm_destroy(h)
+    h = ctypes.c_void_p(lib.lbm_create(b"neohooke2d", b"D2Q9", 64, 64, 1, 0.6, 1e-3, 1e-2))
+    lib.lbm_set_param(h, b"trt_lambda", 0.25)
+    lib.lbm_set_storage(h, lbm.STORAGE["f16ne"])
+    assert lib.lbm_bind(h, ctypes.c_void_p(256), ctypes.c_void_p(512), ctypes.c_void_p(768), None) == lbm.LBM_EINVAL
+    lib.lbm_destroy(h)

@@ -1,0 +1,113 @@
+"""GPU parity of the two-relaxation-time collision (symmetric parts at
+omega+, antisymmetric parts at the field's BGK rate omega-, omega+ from the
+magic parameter) against the oracle's TRT, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mms
+from paper_2607_05668_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2607_05668_amd import lbm  # noqa: E402
+
+MAGIC = 3.0 / 16.0
+
+
+def rel(a, b):
+    return math.sqrt(float(np.sum((a - b) ** 2)) / float(np.sum(b ** 2)))
+
+
+def twin(g, system, lattice, params, trackers):
+    phys = {k: v for k, v in params.items() if k not in ("g_tau", "trt_lambda")}
+    kw = {"omega_plus": g.param("omega_plus")}
+    if trackers:
+        kw.update(omega_tracker=g.param("omega_tracker"), omega_plus_tracker=g.param("omega_plus_tracker"))
+    return oracle.Oracle(system, lattice, g.shape, g.param("dt"), g.param("dx"), 1.0 / g.param("omega"),
+                         g.param("g_tau") if trackers else None, phys, Q0=g.reference, **kw)
+
+
+@pytest.mark.parametrize("storage,lattice,shape,tol", [("f32", "D2Q9", (48, 64), 1e-6),
+                                                      ("f64", "D2Q9", (48, 64), 1e-12),
+                                                      ("f32", "D2Q5", (37, 50), 1e-6),
+                                                      ("f16", "D2Q9", (64, 64), 1e-3)])
+def test_swe_trt_matches_oracle(storage, lattice, shape, tol):
+    """Shallow water from the seeded 8-mode depth field, 300 steps; the
+    FP32 path is the float-float one (only the TRT term b d_ib added)."""
+    print(f"swe2d {lattice} {storage} {shape} TRT 300 steps", flush=True)
+    ny, nx = shape
+    dx = 1.0 / max(shape)
+    dt = 0.2 * dx
+    params = {"g": 1.0, "trt_lambda": MAGIC}
+    g = lbm.Stepper("swe2d", lattice, shape, 0.5 + 2.0 * dt, dt, dx, storage, params)
+    Q = inputs.swe_initial(max(shape))[:, :ny, :nx]
+    g.init(Q)
+    g.step(300)
+    assert g.param("omega_plus") != pytest.approx(g.param("omega"), rel=1e-3)
+    o = twin(g, "swe2d", lattice, params, False)
+    o.init(Q)
+    o.step(300)
+    Qg, Qo = g.moments().cpu().numpy(), o.moments()
+    errs = {"h": rel(Qg[0], Qo[0]), "hu": rel(Qg[1:], Qo[1:])}
+    print("rel L2 vs oracle", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v <= tol, k
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-6), ("f64", 1e-12)])
+def test_cnsf_trt_with_trackers_matches_oracle(storage, tol):
+    """2D compressible NSF (12 fields, trackers with their own omega- and
+    omega+), the paper's Mach-3/2 state, 300 steps."""
+    print(f"cnsf_trk2d D2Q5 {storage} 48x48 TRT 300 steps", flush=True)
+    n = 48
+    mu, K = 3.52 / (1.225 * 340.2), 4980.0 / (287.0 * 1.225 * 340.2)
+    params = {"gamma": 1.4, "mu": mu, "kappa": K, "R_gas": 1.0, "g_tau": 6.0, "trt_lambda": MAGIC}
+    dx = 1.0 / n
+    dt = 2.0 * dx * dx
+    g = lbm.Stepper("cnsf_trk2d", "D2Q5", (n, n), 0.5 + 60.0 * dt, dt, dx, storage, params)
+    fQ, _ = mms.cnsf2d_paper(mu, K)
+    X, Y = inputs.grid2(n)
+    Q = fQ(X, Y, 0.0)
+    g.init(Q)
+    g.step(300)
+    o = twin(g, "cnsf_trk2d", "D2Q5", params, True)
+    o.init(Q)
+    o.step(300)
+    Qg, Qo = g.moments().cpu().numpy(), o.moments()
+    errs = {"rho": rel(Qg[0], Qo[0]), "m": rel(Qg[1:3], Qo[1:3]), "E": rel(Qg[3], Qo[3]), "G": rel(Qg[4:], Qo[4:])}
+    print("rel L2 vs oracle", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v <= tol, k
+
+
+def test_hcnsf_trt_matches_oracle():
+    """3D homogenized NSF with the porosity field, D3Q7, FP32, 60 steps."""
+    print("hcnsf3d_trk14 D3Q7 f32 20^3 TRT 60 steps", flush=True)
+    n = 20
+    pre = inputs.PRESETS["hcnsf256"]
+    params = dict(pre.params, g_tau=pre.g_tau, trt_lambda=MAGIC)
+    dx = 1.0 / n
+    dt = pre.f * dx
+    g = lbm.Stepper("hcnsf3d_trk14", "D3Q7", (n, n, n), 0.5 + 20.0 * dt, dt, dx, "f32", params)
+    B = inputs.hcnsf_coefficients(n, 0.4)
+    g.set_field("coef", B)
+    Q = inputs.hcnsf_exact(n, 0.4)
+    g.init(Q)
+    g.step(60)
+    Bo = g._fields["coef"].cpu().numpy().astype(np.float64).reshape(B.shape)
+    o = twin(g, "hcnsf3d_trk14", "D3Q7", params, True)
+    o.init(Q, b=Bo)
+    o.step(60, b=Bo)
+    Qg, Qo = g.moments().cpu().numpy(), o.moments()
+    errs = {"rho": rel(Qg[0], Qo[0]), "m": rel(Qg[1:4], Qo[1:4]), "E": rel(Qg[4], Qo[4]),
+            "G_u": rel(Qg[5:11], Qo[5:11]), "G_T": rel(Qg[11:], Qo[11:])}
+    print("rel L2 vs oracle", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v <= 1e-6, k
