@@ -193,6 +193,11 @@ def extra_runs(torch, lbm, inputs):
     one("burgers2d_D2Q5_f32_2048", p, 2048, "f32", 200, 40, inputs.burgers_initial(2048))
     p = inputs.PRESETS["euler2048"]
     one("euler2d_D2Q5_f32_2048", p, 2048, "f32", 200, 160, inputs.euler_initial(2048))
+    # the same Euler workload with the functor the compiler slice emitted from
+    # the declared conservation law (flux deviation formed as Phi(Q) - F0)
+    import dataclasses
+    one("gen_euler2d_D2Q5_f32_2048", dataclasses.replace(p, system="gen_euler2d"), 2048, "f32", 200, 160,
+        inputs.euler_initial(2048))
     p = inputs.PRESETS["maxwell2048"]
     one("maxwell2d_D2Q5_f32_2048", p, 2048, "f32", 200, 120, inputs.maxwell_initial(2048))
     p = inputs.PRESETS["allencahn2048"]

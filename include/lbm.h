@@ -95,6 +95,14 @@ enum {                      /* lbm_reduce: what                                 
  *                            sym grad u as 00, 11, 22, 01, 02, 12, grad T;
  *                            14 fields) with a prescribed per-cell porosity
  *                            and solid velocity ("coef" field), Sec. 3
+ *            "gen_euler2d", "gen_advdiff_trk2d", "gen_cnsf_trk2d"
+ *                            the same physics compiled from declared
+ *                            conservation laws (Alg. 1: Split, Cascade,
+ *                            Assemble; the functors are generated at build
+ *                            time); parameters by their declared names
+ *                            (gen_cnsf_trk2d: gamma, mu, kappa, R_gas, g_tau),
+ *                            reference default the paper's MMS background; the
+ *                            max-wave-speed reduction returns 0 for them
  *   Tracker layout (2D): tracker fields follow the conserved fields, two
  *   per tracked field in field order (G_q,0, G_q,1).
  *   lattice: "D2Q5" | "D2Q9" (2D systems) | "D3Q7" (3D systems)

@@ -12,7 +12,8 @@ enum {
     SYS_ADVDIFF = 0, SYS_SWE = 1, SYS_NEOHOOKE = 2, SYS_NSF17 = 3, SYS_BURGERS = 4, SYS_EULER = 5,
     SYS_MAXWELL = 6, SYS_ALLENCAHN = 7, SYS_RELHYDRO = 8, SYS_NSE = 9, SYS_CNSF2D = 10,
     SYS_MHD = 11,
-    SYS_HCNSF = 12
+    SYS_HCNSF = 12,
+    SYS_GEN0 = 100             // generated systems: SYS_GEN0 + index in the registry
 };
 enum { LAT_D2Q5 = 0, LAT_D2Q9 = 1, LAT_D3Q7 = 2 };
 
@@ -94,6 +95,14 @@ const Launchers *lbm_launchers_nse(int lat, int storage);
 const Launchers *lbm_launchers_cnsf2d(int lat, int storage);
 const Launchers *lbm_launchers_mhd(int lat, int storage);
 const Launchers *lbm_launchers_hcnsf(int lat, int storage);
+// generated systems (sys_gen.hip): launchers and registry entries
+const Launchers *lbm_launchers_gen(int gen, int lat, int storage);
+int lbm_gen_count();
+const char *lbm_gen_name(int gen);
+int lbm_gen_fields(int gen, int *D, int *n_conserved, int *npar);
+const char *lbm_gen_param_name(int gen, int j);
+double lbm_gen_param_default(int gen, int j);
+double lbm_gen_reference(int gen, int k);
 const Launchers *lbm_launchers_ne(int sys, int lat);   // storage LBM_F16NE
 hipError_t lbm_launch_copy(void *dst, const void *src, size_t n, hipStream_t s);
 hipError_t lbm_launch_streams(void *dst, const void *src, int nx, int ny, int fields, hipStream_t s);
@@ -115,6 +124,7 @@ struct lbm_state_impl {
     double R_gas = 1.0;
     double eta_drag = 0.1;                 // homogenized NSF: drag time eta
     double trt_lambda = 0.0;               // two-relaxation-time magic parameter (0: BGK)
+    double gen_par[16] = {};               // generated systems: declared parameters
     double trt_a[2] = {0, 0}, trt_b[2] = {0, 0};   // TRT (a, b) of conserved fields, trackers
     int mms_on = 0;
     double mms_amp = 0.05, mms_rho0 = 1.0, mms_p0 = 1.0, mms_u0 = 0.0;

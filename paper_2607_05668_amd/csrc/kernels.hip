@@ -98,6 +98,11 @@ KParams<R> lbm_state_impl::kparams(double t_half) const
         if (sys == SYS_CNSF2D) trk = SysCNSF2D::tracker(k);
         if (sys == SYS_MHD) trk = SysMHD::tracker(k);
         if (sys == SYS_HCNSF) trk = SysHCNSF::tracker(k);
+        if (sys >= SYS_GEN0) {
+            int gd, gnc, gnp;
+            lbm_gen_fields(sys - SYS_GEN0, &gd, &gnc, &gnp);
+            trk = k >= gnc;
+        }
         const double om = trk ? omega_t : omega_c;
         p.omega[k] = (R)om;
         p.delta[k] = (R)(2.0 - om);
@@ -170,6 +175,8 @@ KParams<R> lbm_state_impl::kparams(double t_half) const
     d.cs2_phys = cs_phys * cs_phys;
     d.inv_R_gas = 1.0 / R_gas;
     d.inv_eta = 1.0 / eta_drag;
+    if (sys >= SYS_GEN0)
+        for (int j = 0; j < 16; ++j) d.gen[j] = gen_par[j];
     if (sys == SYS_EULER || sys == SYS_CNSF2D) {
         d.p_ref = (gamma - 1.0) * (Q0[3] - 0.5 * (Q0[1] * Q0[1] + Q0[2] * Q0[2]) / Q0[0]);
         d.H_ref = Q0[3] + d.p_ref;
@@ -192,6 +199,7 @@ KParams<R> lbm_state_impl::kparams(double t_half) const
     p.phys.sq_ref = (R)d.sq_ref;
     p.phys.inv_R_gas = (R)d.inv_R_gas;
     p.phys.inv_eta = (R)d.inv_eta;
+    for (int j = 0; j < 16; ++j) p.phys.gen[j] = (R)d.gen[j];
     for (int j = 0; j < 3; ++j) {
         p.phys.mm0_h0[j] = (R)d.mm0_h0[j];
         p.phys.Hu_ref[j] = (R)d.Hu_ref[j];
@@ -247,6 +255,8 @@ const Launchers *lbm_launchers(int sys, int lat, int storage)
     case SYS_CNSF2D: return lbm_launchers_cnsf2d(lat, storage);
     case SYS_MHD: return lbm_launchers_mhd(lat, storage);
     case SYS_HCNSF: return lbm_launchers_hcnsf(lat, storage);
+    default:
+        if (sys >= SYS_GEN0) return lbm_launchers_gen(sys - SYS_GEN0, lat, storage);
     }
     return nullptr;
 }

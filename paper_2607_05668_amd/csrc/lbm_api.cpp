@@ -46,6 +46,8 @@ int system_id(const char *s)
     if (!std::strcmp(s, "cnsf_trk2d")) return SYS_CNSF2D;
     if (!std::strcmp(s, "mhd_trk2d")) return SYS_MHD;
     if (!std::strcmp(s, "hcnsf3d_trk14")) return SYS_HCNSF;
+    for (int g = 0; g < lbm_gen_count(); ++g)
+        if (!std::strcmp(s, lbm_gen_name(g))) return SYS_GEN0 + g;
     return -1;
 }
 
@@ -60,6 +62,27 @@ int lattice_id(const char *s)
 
 const int kSysK[13] = {3, 3, 6, 17, 1, 4, 3, 3, 3, 7, 12, 18, 14};
 const int kSysD[13] = {2, 2, 2, 3, 2, 2, 2, 2, 2, 2, 2, 2, 3};
+
+// fields, dimension and conserved-field count of any system id
+int sys_K(int sys)
+{
+    if (sys < SYS_GEN0) return kSysK[sys];
+    int d, nc, np;
+    return lbm_gen_fields(sys - SYS_GEN0, &d, &nc, &np);
+}
+int sys_D(int sys)
+{
+    if (sys < SYS_GEN0) return kSysD[sys];
+    int d, nc, np;
+    lbm_gen_fields(sys - SYS_GEN0, &d, &nc, &np);
+    return d;
+}
+int gen_conserved(int sys)
+{
+    int d, nc, np;
+    lbm_gen_fields(sys - SYS_GEN0, &d, &nc, &np);
+    return nc;
+}
 const int kLatQ[3] = {5, 9, 7};
 const int kLatD[3] = {2, 2, 3};
 const double kLatCs2[3] = {1.0 / 3.0, 1.0 / 3.0, 1.0 / 4.0};
@@ -141,13 +164,17 @@ void default_reference(lbm_state *h)
     case SYS_MHD: mhd_default_reference(h); break;
     case SYS_HCNSF: hcnsf_default_reference(h); break;
     case SYS_EULER: euler_default_reference(h); break;
+    default:
+        if (h->sys >= SYS_GEN0)
+            for (int k = 0; k < h->K; ++k) h->Q0[k] = lbm_gen_reference(h->sys - SYS_GEN0, k);
+        break;
     }
 }
 
 bool has_trackers(int sys)
 {
     return sys == SYS_ADVDIFF || sys == SYS_NSF17 || sys == SYS_ALLENCAHN || sys == SYS_NSE || sys == SYS_CNSF2D ||
-           sys == SYS_MHD || sys == SYS_HCNSF;
+           sys == SYS_MHD || sys == SYS_HCNSF || (sys >= SYS_GEN0 && gen_conserved(sys) < sys_K(sys));
 }
 
 size_t arith_bytes(const lbm_state *h) { return h->storage == LBM_F64 ? 8 : 4; }
@@ -189,7 +216,7 @@ lbm_state *lbm_create(const char *system, const char *lattice, int nx, int ny, i
         g_create_error = std::string("unknown lattice '") + (lattice ? lattice : "(null)") + "'";
         return nullptr;
     }
-    if (kSysD[sys] != kLatD[lat]) {
+    if (sys_D(sys) != kLatD[lat]) {
         g_create_error = "lattice dimension does not match the system";
         return nullptr;
     }
@@ -197,12 +224,12 @@ lbm_state *lbm_create(const char *system, const char *lattice, int nx, int ny, i
         g_create_error = "nsf3d_trk17 runs on D3Q7";
         return nullptr;
     }
-    if (nx <= 0 || ny <= 0 || nz <= 0 || (kSysD[sys] == 2 && nz != 1)) {
+    if (nx <= 0 || ny <= 0 || nz <= 0 || (sys_D(sys) == 2 && nz != 1)) {
         g_create_error = "invalid grid (nz must be 1 in 2D)";
         return nullptr;
     }
     const long long C = (long long)nx * ny * nz;
-    if ((long long)kSysK[sys] * kLatQ[lat] * C >= (1LL << 40)) {
+    if ((long long)sys_K(sys) * kLatQ[lat] * C >= (1LL << 40)) {
         g_create_error = "grid too large";
         return nullptr;
     }
@@ -217,7 +244,12 @@ lbm_state *lbm_create(const char *system, const char *lattice, int nx, int ny, i
     h->ny = ny;
     h->nz = nz;
     h->C = C;
-    h->K = kSysK[sys];
+    h->K = sys_K(sys);
+    if (sys >= SYS_GEN0) {
+        int d, nc, np;
+        lbm_gen_fields(sys - SYS_GEN0, &d, &nc, &np);
+        for (int j = 0; j < np; ++j) h->gen_par[j] = lbm_gen_param_default(sys - SYS_GEN0, j);
+    }
     h->Q = kLatQ[lat];
     h->D = kLatD[lat];
     h->tau = tau;
@@ -249,6 +281,18 @@ int lbm_set_param(lbm_state *h, const char *name, double v)
     }
     if (n == "check_subchar") { h->check_subchar = v != 0.0; return LBM_OK; }
     if (h->bound && n != "mms") return fail(h, LBM_EINVAL, "parameters are fixed once bound");
+    if (h->sys >= SYS_GEN0) {
+        const int g = h->sys - SYS_GEN0;
+        int d, nc, np;
+        lbm_gen_fields(g, &d, &nc, &np);
+        for (int j = 0; j < np; ++j)
+            if (n == lbm_gen_param_name(g, j)) { h->gen_par[j] = v; return LBM_OK; }
+        if (nc < h->K && n == "g_tau") {
+            if (!(v > 0)) return fail(h, LBM_EINVAL, "g_tau must be positive");
+            h->g_tau = v;
+            return LBM_OK;
+        }
+    }
     switch (h->sys) {
     case SYS_SWE:
         if (n == "g") { h->g = v; return LBM_OK; }
@@ -428,6 +472,9 @@ int lbm_set_reference(lbm_state *h, const double *Q0)
     if (h->sys == SYS_HCNSF)
         for (int k = 5; k < h->K; ++k)
             if (Q0[k] != 0.0) return fail(h, LBM_EINVAL, "hcnsf3d_trk14: the reference trackers must be zero");
+    if (h->sys >= SYS_GEN0)
+        for (int k = gen_conserved(h->sys); k < h->K; ++k)
+            if (Q0[k] != 0.0) return fail(h, LBM_EINVAL, "generated systems: the reference trackers must be zero");
     for (int k = 0; k < h->K; ++k) h->Q0[k] = Q0[k];
     h->q0_set = true;
     return LBM_OK;

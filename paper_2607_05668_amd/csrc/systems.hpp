@@ -38,6 +38,7 @@ struct Phys {
     R sq_ref;             // ultrarelativistic: sqrt(4 E0^2 - 3 |S0|^2)
     R inv_R_gas;          // 2D compressible NSF: 1 / R (T = p / (R rho))
     R inv_eta;            // homogenized NSF: drag rate 1 / eta
+    R gen[16];            // generated systems: declared parameters, in order
     R H0[4];              // F0 - I (reference deformation minus identity)
     R P0[4];              // first Piola-Kirchhoff stress at F0
 };

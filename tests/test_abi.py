@@ -145,3 +145,21 @@ def test_trt_parameters_and_bgk_only_paths():
     lib.lbm_set_storage(h, lbm.STORAGE["f16ne"])
     assert lib.lbm_bind(h, ctypes.c_void_p(256), ctypes.c_void_p(512), ctypes.c_void_p(768), None) == lbm.LBM_EINVAL
     lib.lbm_destroy(h)
+
+
+def test_default_references():
+    """Each system's default reference state (the shifted form's Q0)."""
+    import numpy as np
+    lib = lbm.load_library()
+    dp = ctypes.POINTER(ctypes.c_double)
+    cases = {b"burgers2d": [0.0], b"maxwell2d": [0.0, 0.0, 0.0], b"allencahn_trk2d": [0.0, 0.0, 0.0],
+             b"swe2d": [1.0, 0.0, 0.0], b"euler2d": [1.0, 3.0, 3.0, 1 / 1.4 / 0.4 + 9.0],
+             b"gen_euler2d": [1.0, 3.0, 3.0, 1 / 1.4 / 0.4 + 9.0], b"gen_advdiff_trk2d": [1.0, 0.0, 0.0]}
+    for name, want in cases.items():
+        h = ctypes.c_void_p(lib.lbm_create(name, b"D2Q5", 16, 16, 1, 0.6, 1e-3, 1e-2))
+        assert h.value, name
+        lib.lbm_set_storage(h, lbm.STORAGE["f64"])
+        out = np.zeros(len(want))
+        assert lib.lbm_get_reference(h, out.ctypes.data_as(dp)) == 0
+        assert np.allclose(out, want, rtol=1e-15, atol=0), name
+        lib.lbm_destroy(h)

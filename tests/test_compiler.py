@@ -1,0 +1,119 @@
+"""The compiler slice (declared conservation law -> gradient-free tracker
+system -> device functor): its Buckingham-Pi scaling against the paper's
+statements, and the compiled fluxes and sources against the oracle's
+hand-written systems at random states.  CPU only."""
+import os
+
+import numpy as np
+import pytest
+import sympy as sp
+
+import oracle
+from paper_2607_05668_amd import compiler as C
+from paper_2607_05668_amd import declared
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_buckingham_pi_scalings():
+    """Sec. 2.6: with mass eliminated through the density and temperature
+    through the gas constant, a velocity scales as (1, -1), the density as
+    (0, 0), and the dynamic viscosity and the thermal conductivity both as a
+    length^2 / time diffusivity (2, -1)."""
+    pq = C.pq_projection([C.DENSITY, C.GAS_CONSTANT])
+    assert pq(C.VELOCITY) == (1, -1)
+    assert pq(C.DENSITY) == (0, 0)
+    assert pq(C.DYNAMIC_VISCOSITY) == (2, -1)
+    assert pq(C.THERMAL_CONDUCTIVITY) == (2, -1)
+    assert pq(C.LENGTH) == (1, 0) and pq(C.TIME) == (0, 1)
+    assert pq(C.PRESSURE) == (2, -2)
+    with pytest.raises(ValueError):
+        C.pq_projection([C.DENSITY])           # temperature left unreferenced
+
+
+def test_lattice_factors_and_tracker_scaling():
+    """Fluxes carry one dt/dx more than their field, sources one dt; a
+    tracker scales as its parent with one inverse length more."""
+    dx, dt = sp.symbols("dx dt", positive=True)
+    for p, q in ((1, -1), (2, -2), (0, 0)):
+        f = C.lattice_factors(p, q, dx, dt)
+        assert sp.simplify(f["flux"] / f["state"] - dt / dx) == 0
+        assert sp.simplify(f["source"] / f["state"] - dt) == 0
+    s = declared.cnsf2d()
+    assert s.pq["G_m0_1"] == (s.pq["m0"][0] - 1, s.pq["m0"][1])
+    assert s.pq["mu"] == (2, -1) and s.pq["kappa"] == (2, -1)
+
+
+def test_split_and_cascade_structure():
+    """Split puts the divergence terms in the flux and minus the rest in
+    the source; Cascade turns grad c into a tracker with the advection-
+    relaxation law, and the 2D NSF stress and heat flux into trackers of
+    every conserved field (chain rule), ordered by parent."""
+    s = declared.advdiff2d()
+    assert s.names == ["c", "G_c_0", "G_c_1"] and s.n_conserved == 1
+    c, g0, g1 = s.fields
+    R = s.params[s.param_names.index("R")]
+    assert sp.simplify(s.source[0] - R * c * (1 - c)) == 0
+    assert sp.simplify(s.source[1] + g0 * s.inv_tau_grad) == 0
+    s = declared.cnsf2d()
+    assert s.names[4:] == ["G_rho_0", "G_rho_1", "G_m0_0", "G_m0_1", "G_m1_0", "G_m1_1", "G_E_0", "G_E_1"]
+    assert all(not e.atoms(C.Partial) for row in s.flux for e in row)
+
+
+CASES = [
+    (declared.euler2d, "euler2d", "D2Q5", {"gamma": 1.4}),
+    (declared.advdiff2d, "advdiff_trk2d", "D2Q5", {"ax": 0.1, "ay": -0.05, "nu": 0.02, "R": 0.7}),
+    (declared.cnsf2d, "cnsf_trk2d", "D2Q5", {"gamma": 1.4, "mu": 0.013, "kappa": 0.05, "R_gas": 1.3}),
+    (declared.nsf3d17, "nsf3d_trk17", "D3Q7", {"gamma": 1.4, "mu": 0.013, "kappa": 0.05}),
+]
+
+
+@pytest.mark.parametrize("decl,system,lattice,par", CASES, ids=[c[1] for c in CASES])
+def test_compiled_system_equals_the_oracle(decl, system, lattice, par):
+    s = decl()
+    K = s.K
+    shape = (4,) * (3 if lattice == "D3Q7" else 2)
+    g_tau = 3.0 if K > s.n_conserved else None
+    o = oracle.Oracle(system, lattice, shape, 0.001, 0.01, 0.6, g_tau, par, Q0=[1.0] + [0.0] * (K - 1))
+    itg = 1.0 / o.params["tau_grad"] if g_tau else 1.0
+    fF, fS = s.numpy_flux_source()
+    pv = [par[n] for n in s.param_names]
+    rng = np.random.default_rng(11)
+    for _ in range(25):
+        q = rng.uniform(-1, 1, K)
+        q[0] = rng.uniform(0.8, 1.2)
+        if system in ("euler2d", "cnsf_trk2d"):
+            q[3] = rng.uniform(4, 6)
+        if system == "nsf3d_trk17":
+            q[4] = rng.uniform(4, 6)
+        Fo, So = o.flux(q)[:, :s.dim], o.source(q)
+        Fg, Sg = fF(q, pv, itg), fS(q, pv, itg)
+        scale = max(1.0, np.abs(Fo).max())
+        assert np.abs(Fg - Fo).max() < 1e-12 * scale
+        assert np.abs(Sg - So).max() < 1e-12 * max(1.0, np.abs(So).max())
+
+
+def test_emitted_header_is_current():
+    """The committed generated header is what the declarations emit now."""
+    from paper_2607_05668_amd import build
+    path = os.path.join(ROOT, "paper_2607_05668_amd", "csrc", "gen_systems.hpp")
+    assert open(path).read() == build.generated_header()
+
+
+@pytest.mark.parametrize("decl", [declared.euler2d, declared.advdiff2d, declared.cnsf2d])
+def test_fluctuation_form_is_the_flux_difference(decl):
+    """The emitted flux deviation equals Phi(Q0 + dQ) - Phi(Q0) (zero
+    tracker references), with the reference terms cancelled symbolically."""
+    s = decl()
+    q0, dq, df = C.fluctuation_form(s)
+    fF, _ = s.numpy_flux_source()
+    f = sp.lambdify([q0, dq, s.params, s.inv_tau_grad], df, "numpy")
+    rng = np.random.default_rng(12)
+    par = list(rng.uniform(0.5, 1.5, len(s.params)))
+    for _ in range(10):
+        Q0 = rng.uniform(0.8, 1.2, s.K)
+        Q0[s.n_conserved:] = 0.0
+        dQ = rng.uniform(-0.1, 0.1, s.K)
+        a = np.array(f(Q0, dQ, par, 3.0))
+        b = fF(Q0 + dQ, par, 3.0) - fF(Q0, par, 3.0)
+        assert np.abs(a - b).max() < 1e-13 * max(1.0, np.abs(b).max())
