@@ -79,11 +79,28 @@ def _random_states(system, shape, rng):
     if system == "neohooke2d":
         F = np.eye(2)[:, :, None, None] + rng.uniform(-0.2, 0.2, (2, 2) + shape)
         return np.concatenate([F.reshape((4,) + shape), rng.uniform(-0.1, 0.1, (2,) + shape)])
-    q = np.zeros((17,) + shape)
+    if system == "burgers2d":
+        return rng.uniform(-1, 1, (1,) + shape)
+    if system in ("maxwell2d", "allencahn_trk2d"):
+        return rng.uniform(-1, 1, (3,) + shape)
+    if system == "relhydro2d":
+        return np.concatenate([rng.uniform(2.5, 3.5, (1,) + shape), rng.uniform(-0.5, 0.5, (2,) + shape)])
+    if system in ("euler2d", "cnsf_trk2d", "nse_trk2d", "mhd_trk2d"):
+        K = {"euler2d": 4, "cnsf_trk2d": 12, "nse_trk2d": 7, "mhd_trk2d": 18}[system]
+        q = rng.uniform(-1, 1, (K,) + shape)
+        q[0] = rng.uniform(0.8, 1.2, shape)
+        q[1:3] = rng.uniform(-0.3, 0.3, (2,) + shape)
+        if system != "nse_trk2d":
+            q[3] = rng.uniform(9.5, 10.5, shape) if system == "mhd_trk2d" else rng.uniform(2.2, 2.8, shape)
+        if system == "mhd_trk2d":
+            q[4:6] = rng.uniform(-0.5, 0.5, (2,) + shape)
+        return q
+    K = 14 if system == "hcnsf3d_trk14" else 17
+    q = np.zeros((K,) + shape)
     q[0] = rng.uniform(0.8, 1.2, shape)
     q[1:4] = rng.uniform(-0.3, 0.3, (3,) + shape)
     q[4] = rng.uniform(2.2, 2.8, shape)
-    q[5:] = rng.uniform(-1, 1, (12,) + shape)
+    q[5:] = rng.uniform(-1, 1, (K - 5,) + shape)
     return q
 
 
@@ -92,7 +109,20 @@ CASES = [("advdiff_trk2d", "D2Q5", {"ax": 0.1, "ay": 0.05, "nu": 0.01}, [1, 0, 0
          ("swe2d", "D2Q5", {"g": 1.0}, [1, 0, 0], None),
          ("neohooke2d", "D2Q9", {"rho0": 1.0, "mu_s": 1.0, "lambda_s": 2.0}, [1, 0, 0, 1, 0, 0], None),
          ("nsf3d_trk17", "D3Q7", {"gamma": 1.4, "mu": 1e-3, "kappa": 5e-3},
-          inputs.NsfMms().reference(), 3.0)]
+          inputs.NsfMms().reference(), 3.0),
+         # the rest of the paper's suite
+         ("burgers2d", "D2Q5", {}, [0.0], None),
+         ("euler2d", "D2Q9", {"gamma": 1.4}, [1.0, 0.3, 0.3, 2.5], None),
+         ("maxwell2d", "D2Q5", {"c": 1.0}, [0.0, 0.0, 0.0], None),
+         ("allencahn_trk2d", "D2Q5", {"nu": 0.01, "R": 1.0}, [0.0, 0.0, 0.0], 6.0),
+         ("relhydro2d", "D2Q5", {}, [3.0, 0.3, 0.3], None),
+         ("nse_trk2d", "D2Q9", {"cs_phys": 1.0, "mu": 0.01}, [1.0] + [0.0] * 6, 6.0),
+         ("cnsf_trk2d", "D2Q5", {"gamma": 1.4, "mu": 0.01, "kappa": 0.04, "R_gas": 1.0},
+          [1.0, 0.2, 0.1, 2.5] + [0.0] * 8, 6.0),
+         ("mhd_trk2d", "D2Q5", {"gamma": 1.4, "mu": 0.01, "kappa": 0.01, "eta": 0.01},
+          [1.0, 0.2, 0.2, 10.0, 0.3, 0.3] + [0.0] * 12, 4.0),
+         ("hcnsf3d_trk14", "D3Q7", {"gamma": 1.4, "mu": 0.01, "kappa": 0.01, "eta": 0.1},
+          [1.0, 0.1, 0.1, 0.1, 2.5] + [0.0] * 9, 3.0)]
 
 
 def _mk(system, lat, params, Q0, g_tau, n, shifted=True, tau=0.51, lam=0.2):
@@ -107,7 +137,7 @@ def test_equilibrium_moments(case):
     """Zeroth and first moments of the initial equilibrium are Q - Q0 and
     (dt/dx)(Phi(Q) - Phi(Q0)) exactly (eq. eq_moments with the shift)."""
     system, lat, params, Q0, g_tau = case
-    n = 6 if system == "nsf3d_trk17" else 8
+    n = 6 if oracle.SYSTEM_DIM[system] == 3 else 8
     o = _mk(system, lat, params, Q0, g_tau, n)
     rng = np.random.default_rng(11)
     Q = _random_states(system, o.shape, rng)
@@ -315,7 +345,7 @@ def test_conservation_with_sources(case):
     """Periodic domain: sum_x Q^{n+1} = sum_x Q^n + dt sum_x S(Q^n) exactly,
     hence conserved rows without sources are invariant."""
     system, lat, params, Q0, g_tau = case
-    n = 6 if system == "nsf3d_trk17" else 12
+    n = 6 if oracle.SYSTEM_DIM[system] == 3 else 12
     o = _mk(system, lat, params, Q0, g_tau, n, lam=0.05)
     rng = np.random.default_rng(2)
     Q = _random_states(system, o.shape, rng)
@@ -343,7 +373,7 @@ def test_shifted_equals_unshifted(case):
     """The equilibrium shift f* = f - f^eq(Q0, F0) is uniform and invariant
     under streaming, so shifted and unshifted FP64 runs agree to rounding."""
     system, lat, params, Q0, g_tau = case
-    n = 6 if system == "nsf3d_trk17" else 12
+    n = 6 if oracle.SYSTEM_DIM[system] == 3 else 12
     rng = np.random.default_rng(4)
     a = _mk(system, lat, params, Q0, g_tau, n, shifted=True, lam=0.05)
     b = _mk(system, lat, params, None, g_tau, n, shifted=False, lam=0.05)
