@@ -205,7 +205,11 @@ int lbm_bind(lbm_state *h, void *pop_a, void *pop_b, void *aux, void *hip_stream
  *            velocity u_s, read by the flux and the source of every step
  *            and by lbm_init_moments (attach it before initialising; without
  *            it every cell is fluid, alpha = 1).  Not with LBM_F16NE.
- * The caller may rewrite the field between steps (on the bound stream) to
+ *   "source" (every system, NB = K): an explicit per-cell source added to
+ *            S_k of every step (eq. lbe_update: evaluated by the caller at
+ *            t + dt/2, e.g. a manufactured-solution forcing).  Not with
+ *            LBM_F16NE.
+ * The caller may rewrite a field between steps (on the bound stream) to
  * prescribe it in time. */
 int lbm_set_field(lbm_state *h, const char *name, const void *dev_ptr);
 

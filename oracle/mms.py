@@ -63,8 +63,8 @@ def swe_topography_expr():
 
 
 @functools.lru_cache(maxsize=None)
-def swe_paper(g: float):
-    """Return (exact(x, y, t) -> [3, ...], forcing(x, y, t) -> [3, ...], b(x, y) -> [2, ...])."""
+def swe_exprs(g: float):
+    """Symbolic (exact fields, forcing, topography gradient) of the SWE MMS."""
     gs = sp.Float(g)
     Q = swe_exact_exprs()
     h, mx, my = Q
@@ -74,9 +74,16 @@ def swe_paper(g: float):
     zb = swe_topography_expr()
     S = [sp.Integer(0), -gs * h * sp.diff(zb, X), -gs * h * sp.diff(zb, Y)]
     res = [sp.diff(Q[k], T) + _div(Phi[k], (X, Y)) - S[k] for k in range(3)]
+    return Q, res, [sp.diff(zb, X), sp.diff(zb, Y)]
+
+
+@functools.lru_cache(maxsize=None)
+def swe_paper(g: float):
+    """Return (exact(x, y, t) -> [3, ...], forcing(x, y, t) -> [3, ...], b(x, y) -> [2, ...])."""
+    Q, res, b = swe_exprs(g)
     fQ = sp.lambdify((X, Y, T), Q, "numpy")
     fS = sp.lambdify((X, Y, T), res, "numpy", cse=True)
-    fb = sp.lambdify((X, Y), [sp.diff(zb, X), sp.diff(zb, Y)], "numpy")
+    fb = sp.lambdify((X, Y), b, "numpy")
     return _wrap2(fQ), _wrap2(fS), _wrap2b(fb)
 
 
@@ -127,8 +134,8 @@ def euler_exact_exprs(rho0=1.0, cs=1.0, gamma=1.4):
 
 
 @functools.lru_cache(maxsize=None)
-def euler_paper(rho0=1.0, cs=1.0, gamma=1.4):
-    """(exact(x, y, t) -> [4, ...], forcing(x, y, t) -> [4, ...])."""
+def euler_exprs(rho0=1.0, cs=1.0, gamma=1.4):
+    """Symbolic (exact fields, forcing) of the Euler MMS."""
     Q, gm = euler_exact_exprs(rho0, cs, gamma)
     rho, mx, my, E = Q
     p = (gm - 1) * (E - (mx ** 2 + my ** 2) / (2 * rho))
@@ -137,6 +144,27 @@ def euler_paper(rho0=1.0, cs=1.0, gamma=1.4):
            [mx * my / rho, my ** 2 / rho + p],
            [(E + p) * mx / rho, (E + p) * my / rho]]
     res = [sp.diff(Q[k], T) + _div(Phi[k], (X, Y)) for k in range(4)]
+    return Q, res
+
+
+def torch_fields(exprs):
+    """f(Xg, Yg, t) -> [K, ...] torch tensor on the device and dtype of Xg,
+    evaluating SymPy expressions of (x, y, t) with torch (test inputs such
+    as a manufactured forcing evaluated next to the GPU stepper)."""
+    import torch
+    fn = sp.lambdify((X, Y, T), list(exprs), "torch", cse=True)
+
+    def f(Xg, Yg, t):
+        tt = torch.as_tensor(t, dtype=Xg.dtype, device=Xg.device)
+        return torch.stack([v if torch.is_tensor(v) and v.shape == Xg.shape else
+                            torch.full_like(Xg, float(v)) for v in fn(Xg, Yg, tt)])
+    return f
+
+
+@functools.lru_cache(maxsize=None)
+def euler_paper(rho0=1.0, cs=1.0, gamma=1.4):
+    """(exact(x, y, t) -> [4, ...], forcing(x, y, t) -> [4, ...])."""
+    Q, res = euler_exprs(rho0, cs, gamma)
     fQ = sp.lambdify((X, Y, T), Q, "numpy")
     fS = sp.lambdify((X, Y, T), res, "numpy", cse=True)
     return _wrap2(fQ), _wrap2(fS)

@@ -57,6 +57,7 @@ struct KParams {
     float inv_scale[LBM_MAXK];
     Phys<R> phys;
     const R *b;                       // per-cell source field [D][C] or null
+    const R *sext;                    // per-cell explicit source [K][C] added to S_k, or null
     MmsParams<R> mms;
 };
 
@@ -140,6 +141,7 @@ struct lbm_state_impl {
     hipStream_t stream = nullptr;
     bool bound = false;
     const void *field_b = nullptr;
+    const void *field_src = nullptr;         // explicit per-cell source [K][cells]
     // time
     long long nsteps = 0;
     const Launchers *L = nullptr;

@@ -226,6 +226,7 @@ KParams<R> lbm_state_impl::kparams(double t_half) const
         p.phys.P0[j] = (R)d.P0[j];
     }
     p.b = (const R *)field_b;
+    p.sext = (const R *)field_src;
     p.mms.on = (sys == SYS_NSF17) ? mms_on : 0;
     p.mms.amp = (R)mms_amp;
     p.mms.rho0 = (R)mms_rho0;

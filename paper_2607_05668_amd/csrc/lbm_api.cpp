@@ -508,6 +508,7 @@ int lbm_bind(lbm_state *h, void *pop_a, void *pop_b, void *aux, void *hip_stream
     if (((uintptr_t)pop_a | (uintptr_t)pop_b | (uintptr_t)aux) & 255u)
         return fail(h, LBM_EINVAL, "buffers must be 256-byte aligned");
     if (has_trackers(h->sys) && !(h->g_tau > 0)) return fail(h, LBM_EINVAL, "set g_tau before binding");
+    if (h->storage == LBM_F16NE && h->field_src) return fail(h, LBM_EINVAL, "no explicit source field with F16NE storage");
     h->L = lbm_launchers(h->sys, h->lat, h->storage);
     if (!h->L) return fail(h, LBM_EINVAL, "no kernel for this system, lattice and storage");
     // Parameters in use.  With single-precision arithmetic the kernels see
@@ -567,6 +568,11 @@ int lbm_set_field(lbm_state *h, const char *name, const void *dev_ptr)
     if (!h || !name) return LBM_EINVAL;
     if (h->sys == SYS_SWE && !std::strcmp(name, "grad_zb")) {
         h->field_b = dev_ptr;
+        return LBM_OK;
+    }
+    if (!std::strcmp(name, "source")) {
+        if (h->storage == LBM_F16NE) return fail(h, LBM_EINVAL, "no explicit source field with F16NE storage");
+        h->field_src = dev_ptr;
         return LBM_OK;
     }
     if (h->sys == SYS_HCNSF && !std::strcmp(name, "coef")) {

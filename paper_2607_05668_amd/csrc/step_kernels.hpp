@@ -255,6 +255,12 @@ __global__ __launch_bounds__((step_block<Sys, St>())) void k_step(const St *__re
     }
     R Sk[K];
     Sys::template source<R, R>(p.phys, dQ, bl, Sk);
+    if (p.sext) {
+        // explicit per-cell source (e.g. a manufactured-solution forcing
+        // evaluated at t + dt/2 by the caller)
+#pragma unroll
+        for (int k = 0; k < K; ++k) Sk[k] += *byte_at(p.sext + k * (size_t)p.C, cell * (I)sizeof(R));
+    }
     if constexpr (Sys::id == SYS_NSF17) {
         if (p.mms.on) {
             R S5[5];

@@ -192,14 +192,16 @@ class Stepper:
     FIELD_COMPONENTS = {"grad_zb": 2, "coef": 4}
 
     def set_field(self, name, value):
-        """Attach a per-cell field: "grad_zb" (swe2d, [2, ...]) or "coef"
-        (hcnsf3d_trk14: alpha, u_s, [4, ...]); keeps a reference."""
+        """Attach a per-cell field: "grad_zb" (swe2d, [2, ...]), "coef"
+        (hcnsf3d_trk14: alpha, u_s, [4, ...]) or "source" (any system: an
+        explicit source [K, ...] added to S_k); keeps a reference.  The
+        tensor may be rewritten in place between steps."""
         if value is None:
             self._fields.pop(name, None)
             self._check(self.lib.lbm_set_field(self.h, name.encode(), None))
             return
         t = self.torch.as_tensor(value, device=self.device, dtype=self.real).contiguous()
-        nb = self.FIELD_COMPONENTS.get(name)
+        nb = self.K if name == "source" else self.FIELD_COMPONENTS.get(name)
         if nb is not None and t.numel() != nb * self.C:
             raise ValueError(f"field {name!r} needs {nb} x {self.C} values, got {t.numel()}")
         self._fields[name] = t

@@ -1,0 +1,156 @@
+"""The GPU stepper under the paper's manufactured-solution forcing, passed
+in as the explicit per-cell source field (evaluated with torch at
+t + dt/2 before each step): parity of the forced path with the oracle, and
+the compressible-Euler convergence study of the validation table at
+N = 64 ... 512 in FP64 and FP32 on the GPU."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mms
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2607_05668_amd import lbm  # noqa: E402
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "mms_printed.json")))
+
+
+def rel(a, b):
+    return math.sqrt(float(np.sum((a - b) ** 2)) / float(np.sum(b ** 2)))
+
+
+def euler_run(n, storage, tau_r, t_end=1.0, oracle_check=False):
+    """Forced Euler MMS on D2Q5, f = 0.05, to t_end; returns (errors vs
+    exact, GPU fields, stepper)."""
+    Q, res = mms.euler_exprs()
+    fQ, fS = mms.torch_fields(Q), mms.torch_fields(res)
+    dx = 1.0 / n
+    dt = 0.05 * dx
+    g = lbm.Stepper("euler2d", "D2Q5", (n, n), 0.5 + tau_r * dt, dt, dx, storage, {"gamma": 1.4})
+    real = torch.float64 if storage == "f64" else torch.float32
+    xs = torch.arange(n, dtype=torch.float64, device="cuda") / n
+    Yg, Xg = torch.meshgrid(xs, xs, indexing="ij")
+    g.init(fQ(Xg, Yg, 0.0))
+    src = torch.zeros((4, n, n), dtype=real, device="cuda")
+    g.set_field("source", src)
+    dt_used = g.param("dt")
+    steps = int(round(t_end / dt_used))
+    for j in range(steps):
+        src.copy_(fS(Xg, Yg, (j + 0.5) * dt_used))
+        g.step(1)
+    Qg = g.moments().cpu().numpy()
+    Qe = fQ(Xg, Yg, steps * dt_used).cpu().numpy()
+    errs = {"rho": rel(Qg[0], Qe[0]), "m": math.hypot(rel(Qg[1], Qe[1]), rel(Qg[2], Qe[2])), "E": rel(Qg[3], Qe[3])}
+    return errs, Qg, g
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-6)])
+def test_forced_path_matches_oracle(storage, tol):
+    """Euler MMS forcing through the source field against the oracle's
+    forcing callback, 32^2, 200 steps (t = 0.3125)."""
+    print(f"euler2d D2Q5 {storage} 32x32 forced, 200 steps", flush=True)
+    n, steps = 32, 200
+    _, Qg, g = euler_run(n, storage, 0.2 if storage == "f64" else 5.0, t_end=steps * 0.05 / n)
+    assert g.steps == steps
+    fQn, fSn = mms.euler_paper()
+    X, Y = np.meshgrid(np.arange(n) / n, np.arange(n) / n, indexing="xy")
+    o = oracle.Oracle("euler2d", "D2Q5", (n, n), g.param("dt"), g.param("dx"), 1.0 / g.param("omega"), None,
+                      {"gamma": 1.4}, Q0=g.reference)
+    o.init(fQn(X, Y, 0.0))
+    o.step(steps, source=lambda t: fSn(X, Y, t))
+    Qo = o.moments()
+    errs = {"rho": rel(Qg[0], Qo[0]), "m": rel(Qg[1:3], Qo[1:3]), "E": rel(Qg[3], Qo[3])}
+    print("rel L2 vs oracle", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v <= tol, k
+
+
+def test_euler_convergence_study_on_the_gpu():
+    """The validation table's compressible-Euler rows on the GPU: FP64 with
+    the double recipe (tau_R = 0.2) reproduces the printed N = 512 errors
+    and LSQ orders; FP32 with the single-precision recipe (tau_R = 5) is
+    compared with FP64 on the same recipe and with the printed FP32 row."""
+    ns = (64, 128, 256, 512)
+    out = {}
+    for storage, tau_r in (("f64", 0.2), ("f64", 5.0), ("f32", 5.0)):
+        es = []
+        for n in ns:
+            print(f"euler2d D2Q5 {storage} tau_R {tau_r} N = {n}", flush=True)
+            e, _, _ = euler_run(n, storage, tau_r)
+            es.append(e)
+        out[(storage, tau_r)] = es
+        print(storage, tau_r, [{k: f"{v:.4e}" for k, v in e.items()} for e in es], flush=True)
+    for k in ("rho", "m", "E"):
+        d = [e[k] for e in out[("f64", 0.2)]]
+        assert d[-1] == pytest.approx(GOLD[f"euler_double_{k}_relL2_N512"], rel=0.01), k
+        assert mms.eoc(ns, d) == pytest.approx(GOLD[f"euler_double_{k}_eoc_L2"], abs=0.03), k
+        s32 = [e[k] for e in out[("f32", 5.0)]]
+        s64 = [e[k] for e in out[("f64", 5.0)]]
+        print(f"{k}: FP32 / FP64 at N = 512: {s32[-1] / s64[-1]:.3f}; printed FP32 row {GOLD[f'euler_float_{k}_relL2_N512']:.4e}"
+              f" (ours {s32[-1]:.4e}), LSQ order ours {mms.eoc(ns, s32):.2f} printed {GOLD[f'euler_float_{k}_eoc_L2']}",
+              flush=True)
+        # single precision follows double precision on the same recipe
+        assert s32[-1] <= 1.05 * s64[-1], k
+        assert s32[-1] <= GOLD[f"euler_float_{k}_relL2_N512"], k
+
+
+def swe_run(n, storage, tau_r, g=10.0):
+    """Forced SWE MMS over the topography z_b on D2Q5, f = 0.2, to t = 1."""
+    Q, res, b = mms.swe_exprs(g)
+    fQ, fS, fb = mms.torch_fields(Q), mms.torch_fields(res), mms.torch_fields(b)
+    dx = 1.0 / n
+    dt = 0.2 * dx
+    st = lbm.Stepper("swe2d", "D2Q5", (n, n), 0.5 + tau_r * dt, dt, dx, storage, {"g": g},
+                     reference=[0.1, 0.03, 0.03])
+    real = torch.float64 if storage == "f64" else torch.float32
+    xs = torch.arange(n, dtype=torch.float64, device="cuda") / n
+    Yg, Xg = torch.meshgrid(xs, xs, indexing="ij")
+    st.set_field("grad_zb", fb(Xg, Yg, 0.0).to(real))
+    st.init(fQ(Xg, Yg, 0.0))
+    src = torch.zeros((3, n, n), dtype=real, device="cuda")
+    st.set_field("source", src)
+    dtu = st.param("dt")
+    steps = int(round(1.0 / dtu))
+    for j in range(steps):
+        src.copy_(fS(Xg, Yg, (j + 0.5) * dtu))
+        st.step(1)
+    Qg = st.moments().cpu().numpy()
+    Qe = fQ(Xg, Yg, steps * dtu).cpu().numpy()
+    return {"h": rel(Qg[0], Qe[0]), "hu": math.hypot(rel(Qg[1], Qe[1]), rel(Qg[2], Qe[2]))}
+
+
+def test_swe_convergence_study_on_the_gpu():
+    """The validation table's shallow-water rows on the GPU (g = 10, the
+    reading of the printed MMS that the oracle pins): FP64 with the double
+    recipe (tau_R = 0.5) against the printed N = 512 errors and LSQ orders;
+    FP32 with the single-precision recipe (tau_R = 2) against FP64 on the
+    same recipe and against the printed FP32 row."""
+    ns = (64, 128, 256, 512)
+    out = {}
+    for storage, tau_r in (("f64", 0.5), ("f64", 2.0), ("f32", 2.0)):
+        es = []
+        for n in ns:
+            print(f"swe2d D2Q5 {storage} tau_R {tau_r} N = {n}", flush=True)
+            es.append(swe_run(n, storage, tau_r))
+        out[(storage, tau_r)] = es
+        print(storage, tau_r, [{k: f"{v:.4e}" for k, v in e.items()} for e in es], flush=True)
+    for k in ("h", "hu"):
+        d = [e[k] for e in out[("f64", 0.5)]]
+        assert d[-1] == pytest.approx(GOLD[f"swe_double_{k}_relL2_N512"], rel=0.05), k
+        assert mms.eoc(ns, d) == pytest.approx(GOLD[f"swe_double_{k}_eoc_L2"], abs=0.05), k
+        s32 = [e[k] for e in out[("f32", 2.0)]]
+        s64 = [e[k] for e in out[("f64", 2.0)]]
+        print(f"{k}: FP32 / FP64 at N = 512: {s32[-1] / s64[-1]:.3f}; printed FP32 row {GOLD[f'swe_float_{k}_relL2_N512']:.4e}"
+              f" (ours {s32[-1]:.4e}), LSQ order ours {mms.eoc(ns, s32):.2f} printed {GOLD[f'swe_float_{k}_eoc_L2']}",
+              flush=True)
+        assert s32[-1] <= 1.05 * s64[-1], k
+        assert s32[-1] <= 1.05 * GOLD[f"swe_float_{k}_relL2_N512"], k
