@@ -112,7 +112,7 @@ def burgers_paper(amp=1.3):
     res = sp.diff(u, T) + sp.diff(u ** 2 / 2, X) + sp.diff(u ** 2 / 2, Y)
     fQ = sp.lambdify((X, Y, T), [u], "numpy")
     fS = sp.lambdify((X, Y, T), [res], "numpy", cse=True)
-    return _wrap2(fQ), _wrap2(fS)
+    return _wrap2(fQ, [u]), _wrap2(fS, [res])
 
 
 # -------------------------------------------------------------- EULER ----
@@ -152,7 +152,8 @@ def torch_fields(exprs):
     evaluating SymPy expressions of (x, y, t) with torch (test inputs such
     as a manufactured forcing evaluated next to the GPU stepper)."""
     import torch
-    fn = sp.lambdify((X, Y, T), list(exprs), "torch", cse=True)
+    # numeric constants folded first (torch's pow takes no plain-number pair)
+    fn = sp.lambdify((X, Y, T), [sp.N(e) for e in exprs], "torch", cse=True)
 
     def f(Xg, Yg, t):
         tt = torch.as_tensor(t, dtype=Xg.dtype, device=Xg.device)
@@ -167,7 +168,7 @@ def euler_paper(rho0=1.0, cs=1.0, gamma=1.4):
     Q, res = euler_exprs(rho0, cs, gamma)
     fQ = sp.lambdify((X, Y, T), Q, "numpy")
     fS = sp.lambdify((X, Y, T), res, "numpy", cse=True)
-    return _wrap2(fQ), _wrap2(fS)
+    return _wrap2(fQ, Q), _wrap2(fS, res)
 
 
 # ------------------------------------------------------------ MAXWELL ----
@@ -185,7 +186,7 @@ def maxwell_paper(amp=0.5, omega=4.0, c=1.0):
     res = [sp.diff(Q[k], T) + _div(Phi[k], (X, Y)) for k in range(3)]
     fQ = sp.lambdify((X, Y, T), Q, "numpy")
     fS = sp.lambdify((X, Y, T), res, "numpy", cse=True)
-    return _wrap2(fQ), _wrap2(fS)
+    return _wrap2(fQ, Q), _wrap2(fS, res)
 
 
 # --------------------------------------------------------- ALLEN-CAHN ----
@@ -223,7 +224,7 @@ def relhydro_paper():
     res = [sp.diff(Q[k], T) + _div(Phi[k], (X, Y)) for k in range(3)]
     fQ = sp.lambdify((X, Y, T), Q, "numpy")
     fS = sp.lambdify((X, Y, T), res, "numpy", cse=True)
-    return _wrap2(fQ), _wrap2(fS)
+    return _wrap2(fQ, Q), _wrap2(fS, res)
 
 
 # ----------------------------------------------------------------- NSE ----
@@ -260,7 +261,7 @@ def nse_paper(rho0=1.0, cs=1.0, U=0.1, mu=0.01):
     res = [sp.diff(Q[k], T) + _div(Phi[k], (X, Y)) for k in range(3)] + [sp.Integer(0)] * 4
     fQ = sp.lambdify((X, Y, T), Q, "numpy")
     fS = sp.lambdify((X, Y, T), res, "numpy", cse=True)
-    return _wrap2(fQ), _wrap2(fS)
+    return _wrap2(fQ, Q), _wrap2(fS, res)
 
 
 # ------------------------------------------------------------- CNSF 2D ----
@@ -370,7 +371,7 @@ def mhd_paper(mu, kappa, eta, gamma=1.4, rho0=1.0, cs=1.0):
     res = [sp.diff(Qc[k], T) + _div(Phi[k], (X, Y)) - S[k] for k in range(6)] + [sp.Integer(0)] * 12
     fQ = sp.lambdify((X, Y, T), Qc + G, "numpy", cse=True)
     fS = sp.lambdify((X, Y, T), res, "numpy", cse=True)
-    return _wrap2(fQ), _wrap2(fS)
+    return _wrap2(fQ, Qc + G), _wrap2(fS, res)
 
 
 # ------------------------------------------------------------ ELASTIC ----
@@ -395,7 +396,7 @@ def neohooke_paper(rho0=1.0, mu_s=1.0, lam_s=2.0, amp=0.06):
     res = [sp.diff(Q[k], T) + _div(Phi[k], (X, Y)) for k in range(6)]
     fQ = sp.lambdify((X, Y, T), Q, "numpy")
     fS = sp.lambdify((X, Y, T), res, "numpy", cse=True)
-    return _wrap2(fQ), _wrap2(fS)
+    return _wrap2(fQ, Q), _wrap2(fS, res)
 
 
 # ---------------------------------------------------------------- NSF ----
@@ -541,9 +542,10 @@ def _broadcast(vals, shape):
     return np.stack([np.broadcast_to(np.asarray(v, dtype=np.float64), shape) for v in vals])
 
 
-def _wrap2(fn):
+def _wrap2(fn, exprs=None):
     def f(Xg, Yg, t):
         return _broadcast(fn(Xg, Yg, t), Xg.shape)
+    f.exprs = exprs           # the SymPy expressions, for other evaluators
     return f
 
 
