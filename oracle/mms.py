@@ -156,9 +156,15 @@ def torch_fields(exprs):
     fn = sp.lambdify((X, Y, T), [sp.N(e) for e in exprs], "torch", cse=True)
 
     def f(Xg, Yg, t):
+        """t: a number (-> [K, *Xg.shape]) or a 1-D tensor of times
+        (-> [len(t), K, *Xg.shape], all steps of a batch at once)."""
         tt = torch.as_tensor(t, dtype=Xg.dtype, device=Xg.device)
-        return torch.stack([v if torch.is_tensor(v) and v.shape == Xg.shape else
-                            torch.full_like(Xg, float(v)) for v in fn(Xg, Yg, tt)])
+        if tt.dim() == 1:
+            tt = tt.reshape((-1,) + (1,) * Xg.dim())
+        shape = torch.broadcast_shapes(Xg.shape, tt.shape)
+        vals = [v if torch.is_tensor(v) else torch.tensor(float(v), dtype=Xg.dtype, device=Xg.device)
+                for v in fn(Xg, Yg, tt)]
+        return torch.stack([v.expand(shape) for v in vals], dim=-Xg.dim() - 1).contiguous()
     return f
 
 
