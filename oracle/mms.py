@@ -465,7 +465,7 @@ def nsf17(gamma, rho0, p0, u0, amp, mu, kappa, tau_grad, force_trackers=False):
             res.append(sp.Integer(0))
     fQ = sp.lambdify((X, Y, Z, T), Q, "numpy", cse=True)
     fS = sp.lambdify((X, Y, Z, T), res, "numpy", cse=True)
-    return _wrap3(fQ), _wrap3(fS)
+    return _wrap3(fQ, Q), _wrap3(fS, res)
 
 
 # -------------------------------------------------------------- HCNSF ----
@@ -540,7 +540,7 @@ def hcnsf_paper(mu, kappa, eta, gamma=1.4, amp=0.2, mach=0.5):
     fQ = sp.lambdify((X, Y, Z, T), Q, "numpy", cse=True)
     fS = sp.lambdify((X, Y, Z, T), res, "numpy", cse=True)
     fB = sp.lambdify((X, Y, Z, T), b, "numpy", cse=True)
-    return _wrap3(fQ), _wrap3(fS), _wrap3(fB)
+    return _wrap3(fQ, Q), _wrap3(fS, res), _wrap3(fB, b)
 
 
 # ------------------------------------------------------------- helpers ----
@@ -561,9 +561,10 @@ def _wrap2b(fn):
     return f
 
 
-def _wrap3(fn):
+def _wrap3(fn, exprs=None):
     def f(Xg, Yg, Zg, t):
         return _broadcast(fn(Xg, Yg, Zg, t), Xg.shape)
+    f.exprs = exprs
     return f
 
 

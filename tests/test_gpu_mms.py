@@ -267,3 +267,155 @@ def test_mhd_rows_on_the_gpu():
               f"{GOLD[f'mhd_float_{k}_relL2_N512']:.4e} (ours {s32:.4e}); FP64 {d[-1][k]:.4e} printed "
               f"{GOLD[f'mhd_double_{k}_relL2_N512']:.4e}", flush=True)
         assert s32 <= 1.05 * s64, k
+
+
+def hcnsf_setup(n, storage, tau_r):
+    from paper_2607_05668_amd import inputs
+    si = GOLD["hcnsf_mms_SI"]
+    mu = si["mu"] / (si["rho0"] * si["cs"])
+    K = si["kappa"] / (si["rho0"] * si["cs"])
+    eta = si["eta"] * si["cs"]
+    fQn, fSn, fBn = mms.hcnsf_paper(mu, K, eta, gamma=si["gamma"])
+    pre = inputs.PRESETS["hcnsf256"]
+    dx = 1.0 / n
+    dt = 0.05 * dx
+    st = lbm.Stepper("hcnsf3d_trk14", "D3Q7", (n, n, n), 0.5 + tau_r * dt, dt, dx, storage,
+                     {"gamma": si["gamma"], "mu": mu, "kappa": K, "eta": eta, "g_tau": pre.g_tau})
+    xs = torch.arange(n, dtype=torch.float64, device="cuda") / n
+    Zg, Yg, Xg = torch.meshgrid(xs, xs, xs, indexing="ij")
+    return st, (fQn, fSn, fBn), (Xg, Yg, Zg)
+
+
+def torch3(fn_np):
+    """torch evaluator of an oracle MMS function of (x, y, z, t)."""
+    import sympy as sp
+    f = sp.lambdify((mms.X, mms.Y, mms.Z, mms.T), [sp.N(e) for e in fn_np], "torch", cse=True)
+
+    def g(Xg, Yg, Zg, t):
+        tt = torch.as_tensor(t, dtype=Xg.dtype, device=Xg.device)
+        if tt.dim() == 1:
+            tt = tt.reshape((-1, 1, 1, 1))
+        shape = torch.broadcast_shapes(Xg.shape, tt.shape)
+        vals = [v if torch.is_tensor(v) else torch.tensor(float(v), dtype=Xg.dtype, device=Xg.device)
+                for v in f(Xg, Yg, Zg, tt)]
+        return torch.stack([v.expand(shape) for v in vals], dim=-4).contiguous()
+    return g
+
+
+def hcnsf_drive(st, fS, fB, G, steps, real):
+    import time
+    Xg, Yg, Zg = G
+    dtu = st.param("dt")
+    batch = max(1, min(64, (1 << 28) // (8 * 18 * Xg.numel())))
+    j, t0, last = 0, time.time(), time.time()
+    while j < steps:
+        if time.time() - last > 30:
+            torch.cuda.synchronize()
+            print(f"  step {j} / {steps}, {time.time() - t0:.0f} s", flush=True)
+            last = time.time()
+        b = min(batch, steps - j)
+        t = (torch.arange(j, j + b, dtype=torch.float64, device="cuda") + 0.5) * dtu
+        S = fS(Xg, Yg, Zg, t).to(real)
+        C = fB(Xg, Yg, Zg, t).to(real)
+        for i in range(b):
+            st.set_field("source", S[i])
+            st.set_field("coef", C[i])
+            st.step(1)
+        j += b
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-6)])
+def test_hcnsf_forced_path_matches_oracle(storage, tol):
+    """The homogenized NSF with the paper's MMS forcing and its moving
+    porosity / solid velocity (both re-attached every step at t + dt/2,
+    the porosity at t = 0 for the initial equilibrium), 16^3, 80 steps,
+    against the oracle with the same forcing and coefficients."""
+    print(f"hcnsf3d_trk14 D3Q7 {storage} 16^3 forced, moving porosity, 80 steps", flush=True)
+    n, steps = 16, 80
+    st, (fQn, fSn, fBn), G = hcnsf_setup(n, storage, 10.0 if storage == "f64" else 20.0)
+    fQ, fS, fB = torch3(fQn.exprs), torch3(fSn.exprs), torch3(fBn.exprs)
+    real = torch.float64 if storage == "f64" else torch.float32
+    Xg, Yg, Zg = G
+    B0 = fB(Xg, Yg, Zg, 0.0).to(real)
+    st.set_field("coef", B0)
+    Q0 = fQ(Xg, Yg, Zg, 0.0)
+    st.init(Q0)
+    hcnsf_drive(st, fS, fB, G, steps, real)
+    Qg = st.moments().cpu().numpy()
+    Xn, Yn, Zn = (a.cpu().numpy() for a in G)
+    o = oracle.Oracle("hcnsf3d_trk14", "D3Q7", (n, n, n), st.param("dt"), st.param("dx"), 1.0 / st.param("omega"),
+                      st.param("g_tau"), dict(zip(("gamma", "mu", "kappa", "eta"), _hc_params())),
+                      Q0=st.reference, omega_tracker=st.param("omega_tracker"))
+    rnd = (lambda a: a) if storage == "f64" else (lambda a: a.astype(np.float32).astype(np.float64))
+    o.init(Q0.cpu().numpy(), b=rnd(fBn(Xn, Yn, Zn, 0.0)))
+    o.step(steps, source=lambda t: rnd(fSn(Xn, Yn, Zn, t)), b=lambda t: rnd(fBn(Xn, Yn, Zn, t)))
+    Qo = o.moments()
+    errs = {"rho": rel(Qg[0], Qo[0]), "m": rel(Qg[1:4], Qo[1:4]), "E": rel(Qg[4], Qo[4]),
+            "G": rel(Qg[5:], Qo[5:])}
+    print("rel L2 vs oracle", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v <= tol, k
+
+
+def _hc_params():
+    si = GOLD["hcnsf_mms_SI"]
+    return (si["gamma"], si["mu"] / (si["rho0"] * si["cs"]), si["kappa"] / (si["rho0"] * si["cs"]),
+            si["eta"] * si["cs"])
+
+
+def hcnsf_errors(n, storage, tau_r):
+    st, (fQn, fSn, fBn), G = hcnsf_setup(n, storage, tau_r)
+    fQ, fS, fB = torch3(fQn.exprs), torch3(fSn.exprs), torch3(fBn.exprs)
+    real = torch.float64 if storage == "f64" else torch.float32
+    Xg, Yg, Zg = G
+    st.set_field("coef", fB(Xg, Yg, Zg, 0.0).to(real))
+    st.init(fQ(Xg, Yg, Zg, 0.0))
+    steps = int(round(1.0 / st.param("dt")))
+    hcnsf_drive(st, fS, fB, G, steps, real)
+    Qg = st.moments().cpu().numpy()
+    Qe = fQ(Xg, Yg, Zg, steps * st.param("dt")).cpu().numpy()
+    return {"rho": rel(Qg[0], Qe[0]), "m": math.sqrt(sum(rel(Qg[a], Qe[a]) ** 2 for a in (1, 2, 3))),
+            "E": rel(Qg[4], Qe[4])}
+
+
+def test_hcnsf_forced_at_32_on_the_gpu():
+    """The 3D homogenized NSF MMS to t = 1 at N = 32 in FP64 and FP32 (the
+    double and single recipes): rho, rho u and E sit 2^(3 x printed order
+    +- 0.2) above the printed N = 256 errors of the same precision's row
+    (FP64: 4.2234e-3, 3.3429e-3, 3.1299e-3, the oracle's values; FP32 with
+    tau_R = 20: 6.9381e-3, 6.5517e-3, 3.8453e-3, within 2^0.04 of the
+    printed single-precision row carried back)."""
+    for storage, tau_r in (("f64", 10.0), ("f32", 20.0)):
+        print(f"hcnsf3d_trk14 D3Q7 {storage} N = 32 forced to t = 1", flush=True)
+        e = hcnsf_errors(32, storage, tau_r)
+        prec = "double" if storage == "f64" else "float"
+        print(storage, {k: f"{v:.4e}" for k, v in e.items()}, flush=True)
+        for k in ("rho", "m", "E"):
+            s = GOLD[f"hcnsf_{prec}_{k}_eoc_L2"]
+            assert 2 ** (3 * s - 0.2) < e[k] / GOLD[f"hcnsf_{prec}_{k}_relL2_N256"] < 2 ** (3 * s + 0.2), (prec, k)
+
+
+@pytest.mark.slow
+def test_hcnsf_rows_on_the_gpu():
+    """N = 128, 256: the GPU FP64 errors at N = 256 against the printed
+    double-precision row, FP32 (tau_R = 20) against FP64 on its recipe (at
+    N = 128) and against the printed single-precision row (at N = 256)."""
+    out = {}
+    for storage, tau_r, ns in (("f64", 10.0, (128, 256)), ("f64", 20.0, (128,)), ("f32", 20.0, (128, 256))):
+        es = []
+        for n in ns:
+            print(f"hcnsf3d_trk14 D3Q7 {storage} tau_R {tau_r} N = {n}", flush=True)
+            es.append(hcnsf_errors(n, storage, tau_r))
+        out[(storage, tau_r)] = es
+        print(storage, tau_r, [{k: f"{v:.4e}" for k, v in e.items()} for e in es], flush=True)
+    for k in ("rho", "m", "E"):
+        d = out[("f64", 10.0)][-1][k]
+        s32, s64 = out[("f32", 20.0)][0][k], out[("f64", 20.0)][0][k]
+        f256 = out[("f32", 20.0)][-1][k]
+        print(f"{k}: FP64 N = 256 {d:.4e} printed {GOLD[f'hcnsf_double_{k}_relL2_N256']:.4e}; FP32 N = 256 "
+              f"{f256:.4e} printed {GOLD[f'hcnsf_float_{k}_relL2_N256']:.4e}; FP32 / FP64 at N = 128 {s32 / s64:.3f}",
+              flush=True)
+        assert d == pytest.approx(GOLD[f"hcnsf_double_{k}_relL2_N256"], rel=0.25), k
+        assert s32 <= 1.05 * s64, k
+        assert f256 == pytest.approx(GOLD[f"hcnsf_float_{k}_relL2_N256"], rel=0.25), k
