@@ -126,7 +126,7 @@ class Oracle:
 
     def __init__(self, system, lattice, shape, dt, dx, tau, g_tau=None, params=None,
                  Q0=None, shifted=True, omega_tracker=None, trt_lambda=None, omega_plus=None,
-                 omega_plus_tracker=None):
+                 omega_plus_tracker=None, regularized=False):
         if LATTICE_DIM[lattice] != SYSTEM_DIM[system]:
             raise ValueError("lattice dimension does not match the system")
         self.lib = _load()
@@ -156,7 +156,9 @@ class Oracle:
             cfg.par[PARAM_INDEX[name]] = float(v)
         # two-relaxation-time collision: the symmetric rate from the magic
         # parameter, or given explicitly (conserved fields, trackers)
-        if trt_lambda is not None or omega_plus is not None:
+        if regularized:
+            cfg.trt = 2
+        elif trt_lambda is not None or omega_plus is not None:
             cfg.trt = 1
             trk = set(TRACKER_FIELDS.get(system, ()))
             for k in range(MAXK):

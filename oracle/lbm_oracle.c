@@ -50,7 +50,8 @@ typedef struct {
     double omega[MAXK];   /* per-field collision rate                       */
     double Q0[MAXK];      /* reference state (zeros when unshifted)          */
     double par[16];       /* physical parameters, indices P_*                */
-    int trt;              /* 1: two-relaxation-time collision                */
+    int trt;              /* collision: 0 BGK, 1 two-relaxation-time,
+                             2 regularized (first-order Hermite projection) */
     double omega_plus[MAXK]; /* TRT: rate of the symmetric parts; omega[] then
                                 relaxes the antisymmetric parts              */
 } oracle_cfg;
