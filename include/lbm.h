@@ -147,12 +147,24 @@ int lbm_num_velocities(const lbm_state *h);
  *                   omega-, the symmetric parts at omega+ (Sec. 2.4 names
  *                   such operators as consuming the same equilibria).  Not
  *                   with LBM_F16NE storage, the moment history or the
+ *                   adjoint (LBM_EINVAL).
+ *                   regularized (0 or 1; default 0): regularized collision
+ *                   (Sec. 2.4, the Latt-Chopard operator with first-order
+ *                   Hermite projection): each field's non-equilibrium part
+ *                   is replaced by w_i c_i . Pi1 / cs^2, Pi1 its first
+ *                   moment, before relaxing at the field's BGK rate, so
+ *                   post_i = feq_i + (1 - omega) w_i c_i . Pi1 / cs^2.  The
+ *                   first-order projection keeps the flux relaxation and
+ *                   drops the symmetric non-equilibrium, which makes it
+ *                   unstable near omega -> 2 on some flows.  Excludes
+ *                   trt_lambda > 0, LBM_F16NE, the moment history and the
  *                   adjoint (LBM_EINVAL). */
 int lbm_set_param(lbm_state *h, const char *name, double v);
 
 /* Read a parameter in use: "dt", "dx", "lambda" (dt/dx), "tau", "omega"
  * (conserved fields), "omega_tracker", "tau_grad", "g_tau", "g", "t0",
- * "trt_lambda", and once bound "omega_plus" / "omega_plus_tracker" (the
+ * "trt_lambda", "regularized", and once bound "omega_plus" /
+ * "omega_plus_tracker" (the
  * symmetric TRT rates; equal to omega / omega_tracker under BGK).  Under TRT
  * the kernels use a = (omega+ + omega-)/2 and b = (omega+ - omega-)/2, in
  * single precision with 2 - a on the 2^-24 grid and b rounded once; omega

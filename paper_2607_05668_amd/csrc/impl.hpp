@@ -125,6 +125,7 @@ struct lbm_state_impl {
     double R_gas = 1.0;
     double eta_drag = 0.1;                 // homogenized NSF: drag time eta
     double trt_lambda = 0.0;               // two-relaxation-time magic parameter (0: BGK)
+    bool regularized = false;              // regularized collision (first-order Hermite projection)
     double gen_par[16] = {};               // generated systems: declared parameters
     double trt_a[2] = {0, 0}, trt_b[2] = {0, 0};   // TRT (a, b) of conserved fields, trackers
     int mms_on = 0;

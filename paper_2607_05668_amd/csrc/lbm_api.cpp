@@ -273,6 +273,11 @@ int lbm_set_param(lbm_state *h, const char *name, double v)
     if (!std::isfinite(v)) return fail(h, LBM_EINVAL, "parameter value is not finite");
     const std::string n(name);
     if (n == "t0") { h->t0 = v; return LBM_OK; }
+    if (n == "regularized") {
+        if (h->bound) return fail(h, LBM_EINVAL, "parameters are fixed once bound");
+        h->regularized = v != 0.0;
+        return LBM_OK;
+    }
     if (n == "trt_lambda") {
         if (h->bound) return fail(h, LBM_EINVAL, "parameters are fixed once bound");
         if (!(v >= 0)) return fail(h, LBM_EINVAL, "trt_lambda must be >= 0 (0: BGK)");
@@ -441,6 +446,7 @@ int lbm_get_param(const lbm_state *h, const char *name, double *v)
     else if (n == "omega") *v = h->bound ? h->omega_c : 1.0 / h->tau;
     else if (n == "omega_tracker") *v = h->bound ? h->omega_t : (h->g_tau > 0 ? 1.0 / (h->g_tau + 1.0) : 0.0);
     else if (n == "trt_lambda") *v = h->trt_lambda;
+    else if (n == "regularized") *v = h->regularized ? 1.0 : 0.0;
     else if (n == "omega_plus" || n == "omega_plus_tracker") {
         const int c = n == "omega_plus" ? 0 : 1;
         if (!h->bound) return LBM_EINVAL;                  // defined once bound
@@ -527,6 +533,8 @@ int lbm_bind(lbm_state *h, void *pop_a, void *pop_b, void *aux, void *hip_stream
         h->omega_t = 2.0 - std::nearbyint((2.0 - h->omega_t) * 16777216.0) / 16777216.0;
         h->tau = 1.0 / h->omega_c;
     }
+    if (h->regularized && (h->trt_lambda > 0 || h->storage == LBM_F16NE))
+        return fail(h, LBM_EINVAL, "the regularized collision excludes trt_lambda and F16NE storage");
     if (h->trt_lambda > 0) {
         if (h->storage == LBM_F16NE) return fail(h, LBM_EINVAL, "two-relaxation-time collision needs F64/F32/F16 storage");
         // omega- is the BGK rate (the flux moment relaxes at it); omega+ from
@@ -649,7 +657,8 @@ int lbm_step_record(lbm_state *h, int n, void *Q_hist_dev)
 {
     if (h && !Q_hist_dev) return fail(h, LBM_EINVAL, "null history pointer");
     if (h && h->storage == LBM_F16NE) return fail(h, LBM_EINVAL, "no moment history with F16NE storage");
-    if (h && h->trt_lambda > 0) return fail(h, LBM_EINVAL, "the moment history and the adjoint are BGK only");
+    if (h && (h->trt_lambda > 0 || h->regularized))
+        return fail(h, LBM_EINVAL, "the moment history and the adjoint are BGK only");
     return run_steps(h, n, Q_hist_dev);
 }
 
@@ -703,7 +712,7 @@ int lbm_adjoint_seed(lbm_state *h, const void *dLdQ_dev, void *lam_dev)
 {
     int rc = check_ready(h);
     if (rc) return rc;
-    if (h->trt_lambda > 0) return fail(h, LBM_EINVAL, "the adjoint is BGK only");
+    if (h->trt_lambda > 0 || h->regularized) return fail(h, LBM_EINVAL, "the adjoint is BGK only");
     if (!h->L->adj_seed) return fail(h, LBM_EINVAL, "no adjoint for this system");
     if (!dLdQ_dev || !lam_dev) return fail(h, LBM_EINVAL, "null pointer");
     const hipError_t e = h->L->adj_seed(*h, dLdQ_dev, lam_dev, h->stream);
@@ -714,7 +723,7 @@ int lbm_adjoint_step(lbm_state *h, int n, void *lam_a, void *lam_b, const void *
 {
     int rc = check_ready(h);
     if (rc) return rc;
-    if (h->trt_lambda > 0) return fail(h, LBM_EINVAL, "the adjoint is BGK only");
+    if (h->trt_lambda > 0 || h->regularized) return fail(h, LBM_EINVAL, "the adjoint is BGK only");
     if (!h->L->adj_step) return fail(h, LBM_EINVAL, "no adjoint for this system");
     if (n < 0 || !lam_a || !lam_b || lam_a == lam_b || (n > 0 && !Q_hist_dev)) return fail(h, LBM_EINVAL, "bad adjoint arguments");
     if (grad_field_dev && !h->field_b) return fail(h, LBM_EINVAL, "no source field attached");
@@ -735,7 +744,7 @@ int lbm_adjoint_to_initial(lbm_state *h, const void *lam0_dev, const double *Q_i
 {
     int rc = check_ready(h);
     if (rc) return rc;
-    if (h->trt_lambda > 0) return fail(h, LBM_EINVAL, "the adjoint is BGK only");
+    if (h->trt_lambda > 0 || h->regularized) return fail(h, LBM_EINVAL, "the adjoint is BGK only");
     if (!h->L->adj_init) return fail(h, LBM_EINVAL, "no adjoint for this system");
     if (!lam0_dev || !Q_init_dev || !dLdQ0_dev) return fail(h, LBM_EINVAL, "null pointer");
     const hipError_t e = h->L->adj_init(*h, lam0_dev, Q_init_dev, dLdQ0_dev, h->stream);

@@ -153,7 +153,10 @@ constexpr int step_block()
     return (sizeof(St) == 8 && Sys::K > 12) ? kBlock : (Sys::K > 6 ? 512 : kBlock);
 }
 
-template <class Sys, class Lat, class St, bool REC, bool NT, bool O32, bool TRT>
+// collision operators of the step kernel
+enum { COLL_BGK = 0, COLL_TRT = 1, COLL_REG = 2 };
+
+template <class Sys, class Lat, class St, bool REC, bool NT, bool O32, int COLL>
 __global__ __launch_bounds__((step_block<Sys, St>())) void k_step(const St *__restrict__ fin, St *__restrict__ fout,
                                                             const KParams<typename Store<St>::R> p,
                                                             typename Store<St>::R *__restrict__ qhist)
@@ -278,7 +281,9 @@ __global__ __launch_bounds__((step_block<Sys, St>())) void k_step(const St *__re
     // velocity, relaxing the symmetric and antisymmetric parts at omega+ and
     // omega- is post_i = f_i + a d_i + b d_ib, a = (omega+ + omega-)/2 (in c1
     // = a - 1 and c2 = a), b = (omega+ - omega-)/2: the BGK update plus
-    // b d_ib.
+    // b d_ib.  Regularized: post_i = e_i + (1 - omega) w_i c_i . Pi1 / cs^2
+    // with Pi1 = sum_i c_i (f_i - e_i), the non-equilibrium part projected
+    // on the first-order Hermite polynomial.
     // The rest population closes the zeroth moment,
     // post_0 = f_0 + dt S + sum_{i>0} (f_i - post_i), an identity of the
     // update (the weights sum to one, the flux enters only odd moments)
@@ -311,7 +316,21 @@ __global__ __launch_bounds__((step_block<Sys, St>())) void k_step(const St *__re
         const R dts = p.dt * Sk[k];
         ExactEq<Lat>::zeroth(dts, s);
         R acc = dts;
+        constexpr bool TRT = COLL == COLL_TRT;
         R bd[Q];                         // TRT: b d_i
+        R P1[D];                         // regularized: sum_i c_i (f_i - e_i)
+        if constexpr (COLL == COLL_REG) {
+#pragma unroll
+            for (int a = 0; a < D; ++a) P1[a] = R(0);
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                R d = f[k][i] - eh[i];
+                if constexpr (PRECISE) d = d - el[i];
+#pragma unroll
+                for (int a = 0; a < D; ++a)
+                    if (lat_c<Lat>(i, a) != 0) P1[a] = lat_c<Lat>(i, a) > 0 ? P1[a] + d : P1[a] - d;
+            }
+        }
         if constexpr (TRT) {
             const R tb = p.tb[k];
 #pragma unroll
@@ -326,7 +345,18 @@ __global__ __launch_bounds__((step_block<Sys, St>())) void k_step(const St *__re
         for (int i = 1; i < Q; ++i) {
             const R fi = f[k][i];
             R post;
-            if constexpr (TRT) {
+            if constexpr (COLL == COLL_REG) {
+                R cp = R(0);
+#pragma unroll
+                for (int a = 0; a < D; ++a)
+                    if (lat_c<Lat>(i, a) != 0) cp = lat_c<Lat>(i, a) > 0 ? cp + P1[a] : cp - P1[a];
+                // (1 - omega) w_i / cs^2 (c_i . Pi1), with w_i / cs^2 = Wn_i / Fden
+                const R rg = (-c1) * (cp * (R(Lat::Wn[i]) / R(Lat::Fden)));
+                if constexpr (PRECISE)
+                    post = eh[i] + ((el[i] + rg) + s[i]);
+                else
+                    post = eh[i] + (rg + s[i]);
+            } else if constexpr (TRT) {
                 if constexpr (PRECISE)
                     post = eh[i] + (fma(c1, eh[i] - fi, fma(c2, el[i], bd[Lat::opp[i]])) + s[i]);
                 else
@@ -709,48 +739,51 @@ struct Impl {
     using R = typename Store<St>::R;
     static unsigned grid(long long C) { return (unsigned)((C + kBlock - 1) / kBlock); }
 
-    template <bool REC, bool NT, bool O32, bool TRT>
+    template <bool REC, bool NT, bool O32, int COLL>
     static void launch_step(const lbm_state_impl &h, const void *fin, void *fout, void *qhist, hipStream_t s,
                             const KParams<R> &p)
     {
         constexpr int B = step_block<Sys, St>();
         const long long tpp = ((long long)h.nx * h.ny + B - 1) / B;    // tiles per z-plane
-        hipLaunchKernelGGL((k_step<Sys, Lat, St, REC, NT, O32, TRT>), dim3((unsigned)(tpp * h.nz)), dim3(B), 0, s,
+        hipLaunchKernelGGL((k_step<Sys, Lat, St, REC, NT, O32, COLL>), dim3((unsigned)(tpp * h.nz)), dim3(B), 0, s,
                            (const St *)fin, (St *)fout, p, (R *)qhist);
     }
-    template <bool REC, bool NT, bool TRT>
+    template <bool REC, bool NT, int COLL>
     static void launch_step(const lbm_state_impl &h, const void *fin, void *fout, void *qhist, hipStream_t s,
                             const KParams<R> &p)
     {
         // the 32-bit form needs one (slab, field) block and the history and
         // source planes below 4 GiB
         if (fits_o32((long long)h.nx * h.ny, Lat::Q, sizeof(St)) && fits_o32(h.C, 1, sizeof(R)))
-            launch_step<REC, NT, true, TRT>(h, fin, fout, qhist, s, p);
+            launch_step<REC, NT, true, COLL>(h, fin, fout, qhist, s, p);
         else
-            launch_step<REC, NT, false, TRT>(h, fin, fout, qhist, s, p);
+            launch_step<REC, NT, false, COLL>(h, fin, fout, qhist, s, p);
     }
     static hipError_t step(const lbm_state_impl &h, const void *fin, void *fout, void *qhist, hipStream_t s)
     {
         const double t_half = h.t0 + (h.nsteps + 0.5) * h.dt;
         const KParams<R> p = h.kparams<R>(t_half);
         const bool nt = 2 * (size_t)Sys::K * Lat::Q * sizeof(St) * (size_t)h.C > kLastLevelCacheBytes;
-        const bool trt = h.trt_lambda > 0;
-        if (qhist && trt) return hipErrorInvalidValue;   // the moment history serves the BGK adjoint
+        const int coll = h.regularized ? COLL_REG : (h.trt_lambda > 0 ? COLL_TRT : COLL_BGK);
+        if (qhist && coll != COLL_BGK) return hipErrorInvalidValue;   // the moment history serves the BGK adjoint
         if constexpr (Sys::K <= 6) {
             if (qhist) {
-                nt ? launch_step<true, true, false>(h, fin, fout, qhist, s, p)
-                   : launch_step<true, false, false>(h, fin, fout, qhist, s, p);
+                nt ? launch_step<true, true, COLL_BGK>(h, fin, fout, qhist, s, p)
+                   : launch_step<true, false, COLL_BGK>(h, fin, fout, qhist, s, p);
                 return hipGetLastError();
             }
         } else {
             if (qhist) return hipErrorInvalidValue;   // no adjoint for the 3D cascade
         }
-        if (trt)
-            nt ? launch_step<false, true, true>(h, fin, fout, qhist, s, p)
-               : launch_step<false, false, true>(h, fin, fout, qhist, s, p);
+        if (coll == COLL_TRT)
+            nt ? launch_step<false, true, COLL_TRT>(h, fin, fout, qhist, s, p)
+               : launch_step<false, false, COLL_TRT>(h, fin, fout, qhist, s, p);
+        else if (coll == COLL_REG)
+            nt ? launch_step<false, true, COLL_REG>(h, fin, fout, qhist, s, p)
+               : launch_step<false, false, COLL_REG>(h, fin, fout, qhist, s, p);
         else
-            nt ? launch_step<false, true, false>(h, fin, fout, qhist, s, p)
-               : launch_step<false, false, false>(h, fin, fout, qhist, s, p);
+            nt ? launch_step<false, true, COLL_BGK>(h, fin, fout, qhist, s, p)
+               : launch_step<false, false, COLL_BGK>(h, fin, fout, qhist, s, p);
         return hipGetLastError();
     }
     static hipError_t init(const lbm_state_impl &h, const double *Q, void *fout, hipStream_t s)
