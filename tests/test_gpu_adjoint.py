@@ -112,13 +112,25 @@ ADJ_CASES = [
 ]
 
 
-@pytest.mark.parametrize("case", ADJ_CASES, ids=[c[0] for c in ADJ_CASES])
+# systems the compiler slice emitted from declared laws, against the oracle's
+# hand-written system of the same physics: their flux and source functors
+# are differentiated by the same dual-number pass
+GEN_ADJ_CASES = [
+    ("gen_euler2d", "D2Q5", {"gamma": 1.4}, inputs.euler_initial, ("acoustic", 0.05, 5.0, None), "euler2d"),
+    ("gen_advdiff_trk2d", "D2Q5", {"ax": 0.1, "ay": 0.05, "nu": 0.01, "R": 0.0}, inputs.advdiff_initial,
+     ("diffusive", 1.9, 50.0, 6.0), "advdiff_trk2d"),
+]
+
+
+@pytest.mark.parametrize("case", ADJ_CASES + GEN_ADJ_CASES, ids=[c[0] for c in ADJ_CASES + GEN_ADJ_CASES])
 def test_adjoint_of_every_system_matches_oracle(case):
     """The generic adjoint kernels (dual-number Jacobian contraction of each
-    system's flux and source) for every 2D system: FP32 forward history and
-    adjoint over 30 steps on a 40^2 grid against the oracle's complex-step
-    adjoint, for L = sum_k w_k . Q_k^N with seeded random weights w."""
-    system, lattice, params, init, (scaling, f, tau_r, g_tau) = case
+    system's flux and source) for every 2D system, the generated ones
+    included: FP32 forward history and adjoint over 30 steps on a 40^2 grid
+    against the oracle's complex-step adjoint, for L = sum_k w_k . Q_k^N
+    with seeded random weights w."""
+    system, lattice, params, init, (scaling, f, tau_r, g_tau) = case[:5]
+    oracle_system = case[5] if len(case) > 5 else system
     n, steps = 40, 30
     print(f"adjoint {system} {lattice} {n}x{n} {steps} steps", flush=True)
     dx, dt, tau = lbm.recipe(n, scaling, f, tau_r)
@@ -134,7 +146,7 @@ def test_adjoint_of_every_system_matches_oracle(case):
     out = g.adjoint_step(steps, lam, tmp, hist)
     dQ0 = g.adjoint_to_initial(out, Q).cpu().numpy()
     trk = {"omega_tracker": g.param("omega_tracker")} if g_tau else {}
-    o = oracle.Oracle(system, lattice, (n, n), g.param("dt"), g.param("dx"), 1.0 / g.param("omega"),
+    o = oracle.Oracle(oracle_system, lattice, (n, n), g.param("dt"), g.param("dx"), 1.0 / g.param("omega"),
                       g.param("g_tau") if g_tau else None, params, Q0=g.reference, **trk)
     o.init(Q)
     ohist = []
