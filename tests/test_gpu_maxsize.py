@@ -1,0 +1,100 @@
+"""Largest grids: a grid whose (slab, field) population block exceeds 4 GiB
+runs the step kernel's 64-bit-offset instantiation (smaller grids run the
+32-bit one).  The oracle cannot step 126 million cells, so the check is a
+property that holds at any size: the scheme is translation invariant on a
+periodic grid, hence a field tiled from a periodic pattern stays tiled, and
+every tile equals the pattern's own run on its small grid, which is in turn
+compared with the oracle.  A wrong 64-bit index (a truncated offset, a wrong
+slab or field base, a wrapped neighbour) breaks the tiling."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2607_05668_amd import inputs, lbm  # noqa: E402
+
+
+def _pattern(nx, ny):
+    """Seeded depth and topography-gradient fields periodic on nx x ny."""
+    def modes(seed, nmodes, kmax, amp):
+        m = inputs.draw_modes(seed, nmodes, kmax, amp)
+        X, Y = np.meshgrid(np.arange(nx) / nx, np.arange(ny) / ny, indexing="xy")
+        v, gx, gy = np.zeros((ny, nx)), np.zeros((ny, nx)), np.zeros((ny, nx))
+        for a, b, p, A in zip(m.kx, m.ky, m.phi, m.amp):
+            arg = 2 * math.pi * (a * X + b * Y) + p
+            v += A * np.cos(arg)
+            gx -= A * np.sin(arg) * 2 * math.pi * a
+            gy -= A * np.sin(arg) * 2 * math.pi * b
+        return v, gx, gy
+    h, _, _ = modes(inputs.SEED_SWE_H, 8, 8, 0.05)
+    _, bx, by = modes(inputs.SEED_TOPOGRAPHY, 8, 4, 0.1 / 8)
+    return np.stack([1.0 + h, np.zeros_like(h), np.zeros_like(h)]), np.stack([bx, by])
+
+
+@pytest.mark.parametrize("storage,ry,rx,tol", [
+    ("f32", 277, 246, 1e-6),      # 10249 x 12300 cells
+    ("f16", 370, 350, 1e-3),      # 13690 x 17500 cells
+    ("f16ne", 370, 350, 1e-3),
+])
+def test_swe_64bit_offsets_tiled_grid(storage, ry, rx, tol):
+    ny0, nx0 = 37, 50
+    ny, nx = ny0 * ry, nx0 * rx
+    K, Q = 3, 9
+    s = 4 if storage == "f32" else 2
+    assert nx * ny * Q * s > 0xFFFFFFFF            # one field's block is beyond 32-bit byte offsets
+    assert (nx * ny) % 256 != 0                    # ragged last tile
+    need = (2 * K * Q * s + K * 8 + K * 4 + 2 * 4 + (2 * K * 4 if storage == "f16ne" else 0)) * nx * ny
+    free, _ = torch.cuda.mem_get_info()
+    if free < need + (4 << 30):
+        pytest.skip(f"needs {need / 2**30:.0f} GiB of device memory, {free / 2**30:.0f} free")
+    steps = 60
+    dx = 1.0 / 64
+    dt = 0.2 * dx
+    tau = 0.5 + 2.0 * dt
+    Qp, bp = _pattern(nx0, ny0)
+    print(f"swe2d D2Q9 {storage} {nx}x{ny} (64-bit offsets) tiled from {nx0}x{ny0}, {steps} steps", flush=True)
+
+    small = lbm.Stepper("swe2d", "D2Q9", (ny0, nx0), tau, dt, dx, storage, {"g": 1.0})
+    small.set_field("grad_zb", bp)
+    small.init(Qp)
+    small.step(steps)
+    Qs = small.moments(dtype=torch.float32)
+
+    big = lbm.Stepper("swe2d", "D2Q9", (ny, nx), tau, dt, dx, storage, {"g": 1.0})
+    big.set_field("grad_zb", torch.as_tensor(bp, dtype=torch.float32, device="cuda").repeat(1, ry, rx))
+    Qbig0 = torch.as_tensor(Qp, device="cuda").repeat(1, ry, rx)
+    big.init(Qbig0)
+    del Qbig0
+    big.step(steps)
+    Qb = big.moments(dtype=torch.float32)
+    torch.cuda.synchronize()
+    print("stepped", flush=True)
+
+    tiles = Qb.view(K, ry, ny0, rx, nx0)
+    first = tiles[:, :1, :, :1, :]
+    same = bool(torch.equal(tiles, first.expand_as(tiles)))
+    d_small = float((first[:, 0, :, 0, :] - Qs).abs().max())
+    print(f"all {ry * rx} tiles bit-identical: {same}; max |tile - small grid| {d_small:.3e}", flush=True)
+    Qt = first[:, 0, :, 0, :].double().cpu().numpy()
+    del big, Qb, tiles, first
+    torch.cuda.empty_cache()
+    assert same
+    assert d_small <= 1e-6
+
+    o = oracle.Oracle("swe2d", "D2Q9", (ny0, nx0), small.param("dt"), small.param("dx"), 1.0 / small.param("omega"),
+                      None, {"g": 1.0}, Q0=small.reference)
+    o.init(Qp)
+    o.step(steps, b=bp)
+    Qo = o.moments()
+    eh = math.sqrt(float(np.sum((Qt[0] - Qo[0]) ** 2)) / float(np.sum(Qo[0] ** 2)))
+    em = math.sqrt(float(np.sum((Qt[1:] - Qo[1:]) ** 2)) / float(np.sum(Qo[1:] ** 2)))
+    print(f"tile vs oracle rel L2 h {eh:.3e} hu {em:.3e}", flush=True)
+    assert eh <= tol and em <= tol
