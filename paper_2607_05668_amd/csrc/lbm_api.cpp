@@ -275,6 +275,7 @@ int lbm_set_param(lbm_state *h, const char *name, double v)
     if (n == "t0") { h->t0 = v; return LBM_OK; }
     if (n == "regularized") {
         if (h->bound) return fail(h, LBM_EINVAL, "parameters are fixed once bound");
+        if (v != 0.0 && v != 1.0) return fail(h, LBM_EINVAL, "regularized is 0 or 1");
         h->regularized = v != 0.0;
         return LBM_OK;
     }

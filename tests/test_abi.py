@@ -169,11 +169,13 @@ def test_regularized_parameter_rules():
     lib = lbm.load_library()
     v = ctypes.c_double()
     h = ctypes.c_void_p(lib.lbm_create(b"swe2d", b"D2Q9", 64, 64, 1, 0.6, 1e-3, 1e-2))
+    assert lib.lbm_set_param(h, b"regularized", 0.5) == lbm.LBM_EINVAL
     assert lib.lbm_set_param(h, b"regularized", 1.0) == 0
     assert lib.lbm_get_param(h, b"regularized", ctypes.byref(v)) == 0 and v.value == 1.0
     assert lib.lbm_set_param(h, b"trt_lambda", 0.25) == 0
     assert lib.lbm_bind(h, ctypes.c_void_p(256), ctypes.c_void_p(512), ctypes.c_void_p(768), None) == lbm.LBM_EINVAL
     assert lib.lbm_set_param(h, b"trt_lambda", 0.0) == 0
     assert lib.lbm_bind(h, ctypes.c_void_p(256), ctypes.c_void_p(512), ctypes.c_void_p(768), None) == 0
+    assert lib.lbm_set_param(h, b"regularized", 0.0) == lbm.LBM_EINVAL    # fixed once bound
     assert lib.lbm_step_record(h, 1, ctypes.c_void_p(1024)) == lbm.LBM_EINVAL
     lib.lbm_destroy(h)
