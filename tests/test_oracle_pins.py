@@ -684,7 +684,7 @@ def test_neohooke_mms_second_order():
     tau_R = 0.2 converges at second order (printed EOC 2.00 for F, 1.99 for
     v) on D2Q9, N = 32 -> 64 (oracle: 2.01, 2.03).  The error magnitudes
     depend on the nondimensional moduli, which the paper does not print;
-    mu_s/rho0 = 1, lambda_s/rho0 = 2 is this build's reading (magnitude
+    mu_s/rho0 = 1, lambda_s/rho0 = 2 is this library's reading (magnitude
     unpinned)."""
     fQ, fS = mms.neohooke_paper()
     e = []
