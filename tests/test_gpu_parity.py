@@ -184,6 +184,34 @@ def test_neohooke_matches_oracle(storage, tol):
     assert ev <= tol
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16", "f16ne"])
+def test_neohooke_full_size_tiles(storage):
+    """C5 at its full size and launch shape (2048^2, non-temporal stores,
+    2000 steps) through a property that holds at any size: the 256^2 parity
+    field tiled 8 x 8, stepped with the 256^2 grid's dt, dx and tau.  The
+    scheme is translation invariant on the periodic grid, so the 64 tiles
+    stay bit-identical to each other and equal to the 256^2 run, which
+    test_neohooke_matches_oracle compares with the oracle."""
+    print(f"neohooke2d D2Q9 {storage} 2048x2048 tiled from 256x256, 2000 steps", flush=True)
+    p = inputs.PRESETS["neohooke2048"]
+    dx, dt, tau = lbm.recipe(256, p.scaling, p.f, p.tau_r)
+    Q = inputs.neohooke_initial(256)
+    small = lbm.Stepper(p.system, p.lattice, (256, 256), tau, dt, dx, storage, dict(p.params))
+    small.init(Q)
+    small.step(2000)
+    Qs = small.moments()
+    big = lbm.Stepper(p.system, p.lattice, (2048, 2048), tau, dt, dx, storage, dict(p.params))
+    big.init(torch.as_tensor(Q, device="cuda").repeat(1, 8, 8))
+    big.step(2000)
+    tiles = big.moments().view(6, 8, 256, 8, 256)
+    first = tiles[:, :1, :, :1, :]
+    same = bool(torch.equal(tiles, first.expand_as(tiles)))
+    d = float((first[:, 0, :, 0, :] - Qs).abs().max())
+    print(f"64 tiles bit-identical: {same}; max |tile - 256^2 run| {d:.3e}", flush=True)
+    assert same
+    assert d <= 1e-6 * float(Qs.abs().max())
+
+
 def test_reductions_match_moments():
     g = lbm.Stepper("swe2d", "D2Q9", (96, 128), 0.52, 0.2 / 128, 1.0 / 128, "f32", {"g": 1.0})
     Q = np.stack([1 + 0.1 * np.random.default_rng(0).normal(size=(96, 128)), np.zeros((96, 128)),
