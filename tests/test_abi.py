@@ -179,3 +179,12 @@ def test_regularized_parameter_rules():
     assert lib.lbm_set_param(h, b"regularized", 0.0) == lbm.LBM_EINVAL    # fixed once bound
     assert lib.lbm_step_record(h, 1, ctypes.c_void_p(1024)) == lbm.LBM_EINVAL
     lib.lbm_destroy(h)
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """No CPU fallback: without the built HIP library the binding raises
+    instead of computing anything."""
+    monkeypatch.setattr(lbm, "LIB_PATH", str(tmp_path / "liblbm.so"))
+    monkeypatch.setattr(lbm, "_lib", None)
+    with pytest.raises(ImportError, match="not built"):
+        lbm.load_library()
