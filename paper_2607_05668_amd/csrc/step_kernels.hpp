@@ -143,14 +143,15 @@ __device__ inline void nsf_mms_source(const MmsParams<R> &m, const Phys<R> &p, R
 // values live per cell: a 512-thread workgroup (two waves per SIMD) caps a
 // wave at 256 of the SIMD's 512 registers per lane, so two waves share each
 // SIMD and one hides the other's loads (in FP32 it needs 230, no spills).
-// In FP64 the largest states (more than 12 fields) need more than 256 even
+// In FP64 the largest states (12 fields and more) need more than 256 even
 // so and would spill to scratch; a 256-thread workgroup lets one wave per
 // SIMD keep the overflow in accumulation registers instead (resistive MHD
-// 1.77 -> 1.16 ms, homogenized NSF 6.07 -> 5.19 ms per step).
+// 1.77 -> 1.16 ms, homogenized NSF 6.07 -> 5.19 ms, 2D compressible NSF
+// 778 -> 770 us per step).
 template <class Sys, class St>
 constexpr int step_block()
 {
-    return (sizeof(St) == 8 && Sys::K > 12) ? kBlock : (Sys::K > 6 ? 512 : kBlock);
+    return (sizeof(St) == 8 && Sys::K >= 12) ? kBlock : (Sys::K > 6 ? 512 : kBlock);
 }
 
 // collision operators of the step kernel
