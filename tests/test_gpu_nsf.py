@@ -122,3 +122,43 @@ def test_nsf17_full_size_on_the_oracle_convergence_line():
         order = mms.eoc(ns, [errs[n][k] for n in ns])
         print(k, "EOC", f"{order:.3f}")
         assert 1.6 < order < 2.3, k
+
+
+@pytest.mark.parametrize("forced", [False, True])
+def test_nsf17_full_size_launch_tiles(forced):
+    """C3 in its full-size launch shape (256^3, non-temporal stores,
+    512-thread workgroups) at the 32^3 grid's spacing, so that the initial
+    fields, and the in-kernel manufactured forcing, repeat every 32 cells;
+    the 32^3 run is the one test_nsf17_mms_fp32_matches_oracle compares with
+    the oracle.  Unforced, translation invariance makes all 512 tiles equal
+    the 32^3 run bit for bit.  Forced, the sine arguments of the forcing
+    reach 16 pi instead of 2 pi, so their float rounding is 8x larger
+    (16 pi 2^-24 = 3.0e-6 absolute): the conserved fields stay within the
+    FP32 bar 1e-6 and the gradient trackers, which carry the forcing's
+    derivatives, within 2e-5."""
+    print(f"nsf3d_trk17 D3Q7 f32 256^3 at the 32^3 spacing, 200 steps, forced={forced}", flush=True)
+    pre = inputs.PRESETS["nsf256"]
+    m = inputs.NsfMms()
+    steps = 200
+    dx, dt, tau = lbm.recipe(32, pre.scaling, pre.f, pre.tau_r)
+    params = dict(pre.params, g_tau=pre.g_tau, mms=1.0 if forced else 0.0)
+    Q = inputs.nsf_exact(32, 0.0, m)
+    small = lbm.Stepper(pre.system, pre.lattice, (32, 32, 32), tau, dt, dx, "f32", params)
+    small.init(Q)
+    small.step(steps)
+    Qs = small.moments().view(17, 1, 32, 1, 32, 1, 32)
+    big = lbm.Stepper(pre.system, pre.lattice, (256, 256, 256), tau, dt, dx, "f32", params)
+    big.init(torch.as_tensor(Q, device="cuda").repeat(1, 8, 8, 8))
+    big.step(steps)
+    t = big.moments().view(17, 8, 32, 8, 32, 8, 32)
+    if not forced:
+        same = bool(torch.equal(t, Qs.expand_as(t)))
+        print(f"all 512 tiles bit-identical to the 32^3 run: {same}", flush=True)
+        assert same
+        return
+    for k, s in GROUPS.items():
+        ref = Qs[s].expand_as(t[s])
+        e = math.sqrt(float(torch.sum((t[s] - ref) ** 2) / torch.sum(ref ** 2)))
+        emax = float((t[s] - ref).abs().max() / ref.abs().max())
+        print(f"{k}: rel L2 of the 512 tiles against the 32^3 run {e:.2e}, max {emax:.2e}", flush=True)
+        assert e <= (2e-5 if k.startswith("G") else 1e-6), k
