@@ -36,8 +36,12 @@ Cases:
 """
 from __future__ import annotations
 
+import ctypes
 import functools
+import hashlib
 import math
+import os
+import subprocess
 
 import numpy as np
 import sympy as sp
@@ -579,3 +583,51 @@ def eoc(ns, errs):
     x = np.log2(np.asarray(ns, dtype=float))
     y = np.log2(np.asarray(errs, dtype=float))
     return -float(np.polyfit(x, y, 1)[0])
+
+
+# ------------------------------------------------ compiled evaluation ----
+_GEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_gen")
+
+
+def compiled(f3):
+    """The same SymPy expressions as the 3D field function ``f3`` (made by
+    ``_wrap3``), evaluated by generated C: common subexpressions eliminated
+    by SymPy, each printed with ``ccode`` (17 significant digits), one
+    OpenMP loop over the grid points, gcc -O2 without FMA contraction.  The
+    values agree with numpy's evaluation of the same expressions up to
+    rounding order (a few 1e-16 relative); it is some 20 times faster on a
+    64^3 grid, which is what lets the 3D parity tests run the oracle for
+    hundreds of steps."""
+    exprs = [sp.sympify(e) for e in f3.exprs]
+    repl, red = sp.cse(exprs)
+    body = [f"        const double {s} = {sp.ccode(e)};" for s, e in repl]
+    body += [f"        out[(size_t){k} * n + j] = {sp.ccode(e)};" for k, e in enumerate(red)]
+    src = ("#include <math.h>\n#include <stddef.h>\n"
+           "void eval(size_t n, const double *X, const double *Y, const double *Z, double t, double *out)\n"
+           "{\n#pragma omp parallel for schedule(static)\n    for (size_t j = 0; j < n; ++j) {\n"
+           "        const double x = X[j], y = Y[j], z = Z[j];\n"
+           "        (void)x; (void)y; (void)z; (void)t;\n" + "\n".join(body) + "\n    }\n}\n")
+    key = hashlib.sha256(src.encode()).hexdigest()[:20]
+    os.makedirs(_GEN_DIR, exist_ok=True)
+    so = os.path.join(_GEN_DIR, f"f_{key}.so")
+    if not os.path.exists(so):
+        c = os.path.join(_GEN_DIR, f"f_{key}.c")
+        with open(c, "w") as fh:
+            fh.write(src)
+        tmp = so + f".tmp{os.getpid()}"
+        subprocess.run(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared", c, "-o", tmp, "-lm"],
+                       check=True)
+        os.replace(tmp, so)
+    lib = ctypes.CDLL(so)
+    P = ctypes.POINTER(ctypes.c_double)
+    lib.eval.argtypes = [ctypes.c_size_t, P, P, P, ctypes.c_double, P]
+    K = len(exprs)
+
+    def f(Xg, Yg, Zg, t):
+        Xc, Yc, Zc = (np.ascontiguousarray(np.broadcast_to(a, Xg.shape), dtype=np.float64) for a in (Xg, Yg, Zg))
+        out = np.empty((K,) + Xg.shape)
+        lib.eval(Xc.size, Xc.ctypes.data_as(P), Yc.ctypes.data_as(P), Zc.ctypes.data_as(P), float(t),
+                 out.ctypes.data_as(P))
+        return out
+    f.exprs = f3.exprs
+    return f

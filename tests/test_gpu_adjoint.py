@@ -1,12 +1,20 @@
 """GPU discrete adjoint (shallow water with topography source): the FP32
 adjoint kernels against the FP64 oracle's complex-step adjoint, and the full
 512^2 x 500-step checkpointed rollout against central finite differences of
-the FP64 forward on 16 seeded directions (tolerance 1e-4 relative)."""
+the FP64 oracle's forward on 16 seeded directions (tolerance 1e-4
+relative)."""
+import json
+import os
+
 import numpy as np
 import pytest
 
 import oracle
 from paper_2607_05668_amd import inputs
+
+import parity
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 pytestmark = pytest.mark.gpu
 
@@ -34,9 +42,9 @@ def test_adjoint_matches_oracle_adjoint_small():
     dL = (hN - torch.tensor(tgt, device="cuda")) / (n * n)
     gh, gb = run.backward(dL)
     gh, gb = gh.cpu().numpy(), gb.cpu().numpy().astype(np.float64)
-    # oracle twin with the stepper's parameters in use
-    o = oracle.Oracle("swe2d", "D2Q9", (n, n), s.param("dt"), s.param("dx"), 1.0 / s.param("omega"), None,
-                      {"g": 1.0}, Q0=s.reference)
+    # oracle twin with the stepper's parameters in use, checked against the recipe
+    kw = parity.scheme(s, *parity.recipe(n, "acoustic", 0.2, 2.0), Q0=[1.0, 0.0, 0.0])
+    o = oracle.Oracle("swe2d", "D2Q9", (n, n), kw["dt"], kw["dx"], kw["tau"], None, {"g": 1.0}, Q0=kw["Q0"])
     bf = np.float32(b).astype(np.float64)
     Q = np.stack([h0, 0 * h0, 0 * h0])
     o.init(Q)
@@ -53,46 +61,43 @@ def test_adjoint_matches_oracle_adjoint_small():
     assert _rel(gb, ob) <= 1e-4
 
 
-def _loss(runner, h0, b, tgt):
-    hN = runner.forward(h0, b)
-    return 0.5 * torch.mean((hN - tgt) ** 2).item()
-
-
 def test_full_rollout_gradient_matches_central_differences():
     """The adjoint workload: 512^2, 500 steps, checkpoint every 50, FP32
     forward and adjoint; L = mean((h^N - h_tgt)^2)/2; directional
     derivatives along 16 N(0,1) directions (8 in h0, 8 in b, seed 4) against
-    FP64 central differences (eps 1e-6)."""
-    print("adjoint swe2d D2Q9 512x512 500 steps ckpt 50 vs FD", flush=True)
+    central differences (eps 1e-6) of the FP64 oracle's forward on the
+    configuration's recipe, which tests/golden/make_c4_fd.py computed (it
+    calls only the oracle; several CPU minutes)."""
+    print("adjoint swe2d D2Q9 512x512 500 steps ckpt 50 vs oracle FD", flush=True)
+    with open(os.path.join(GOLDEN, "c4_fd.json")) as fh:
+        ref = json.load(fh)
     p = inputs.PRESETS["sweadj512"]
     n, steps = p.n, p.steps
+    assert (ref["n"], ref["steps"], ref["f"], ref["tau_r"]) == (n, steps, p.f, p.tau_r)
     run = rollout.SweRollout(n=n, steps=steps, ckpt=50)
+    # the stepper runs the oracle's recipe up to the single-precision roundings
+    dx, dt, tau = parity.recipe(n, p.scaling, p.f, p.tau_r)
+    assert (dx, dt, tau) == (ref["dx"], ref["dt"], ref["tau"])
+    parity.scheme(run.stepper, dx, dt, tau, Q0=[1.0, 0.0, 0.0])
     h0 = torch.tensor(inputs.swe_height(n), device="cuda", requires_grad=True)
     b = torch.tensor(inputs.topography_gradient(n), device="cuda", dtype=torch.float32, requires_grad=True)
     tgt = torch.tensor(inputs.swe_height(n, seed=inputs.SEED_SWE_TARGET), device="cuda")
     hN = rollout.rollout(h0, b, run)
     loss = 0.5 * torch.mean((hN - tgt) ** 2)
+    print(f"loss {loss.item():.12e} (oracle FP64 {ref['loss']:.12e})", flush=True)
+    assert loss.item() == pytest.approx(ref["loss"], rel=1e-5)
     loss.backward()
-    gh, gb = h0.grad.double(), b.grad.double()
-    fd_run = rollout.SweRollout(n=n, steps=steps, ckpt=50, storage="f64")
-    rng = np.random.default_rng(inputs.SEED_FD_DIRECTIONS)
-    eps = 1e-6
-    h0d, bd = h0.detach(), b.detach().double()
+    gh, gb = h0.grad.double().cpu().numpy(), b.grad.double().cpu().numpy()
+    rng = np.random.default_rng(ref["seed_directions"])
     worst = 0.0
-    for j in range(16):
-        d = torch.tensor(rng.normal(size=(n, n) if j < 8 else (2, n, n)), device="cuda")
-        if j < 8:
-            lp = _loss(fd_run, h0d + eps * d, bd, tgt)
-            lm = _loss(fd_run, h0d - eps * d, bd, tgt)
-            ad = torch.sum(gh * d).item()
-        else:
-            lp = _loss(fd_run, h0d, bd + eps * d, tgt)
-            lm = _loss(fd_run, h0d, bd - eps * d, tgt)
-            ad = torch.sum(gb * d).item()
-        fd = (lp - lm) / (2 * eps)
+    for j, row in enumerate(ref["rows"]):
+        d = rng.normal(size=(n, n) if j < 8 else (2, n, n))
+        assert float(np.sum(d)) == pytest.approx(row["d_sum"], rel=1e-12, abs=1e-9)
+        ad = float(np.sum((gh if j < 8 else gb) * d))
+        fd = row["fd"]
         err = abs(ad - fd) / abs(fd)
         worst = max(worst, err)
-        print(f"direction {j}: adjoint {ad:.10e} FD {fd:.10e} rel {err:.2e}", flush=True)
+        print(f"direction {j}: adjoint {ad:.10e} oracle FD {fd:.10e} rel {err:.2e}", flush=True)
         assert err <= 1e-4
     print(f"worst relative FD disagreement {worst:.3e}")
 
@@ -133,7 +138,7 @@ def test_adjoint_of_every_system_matches_oracle(case):
     oracle_system = case[5] if len(case) > 5 else system
     n, steps = 40, 30
     print(f"adjoint {system} {lattice} {n}x{n} {steps} steps", flush=True)
-    dx, dt, tau = lbm.recipe(n, scaling, f, tau_r)
+    dx, dt, tau = parity.recipe(n, scaling, f, tau_r)
     prm = dict(params, **({"g_tau": g_tau} if g_tau else {}))
     g = lbm.Stepper(system, lattice, (n, n), tau, dt, dx, "f32", prm)
     Q = init(n)
@@ -145,9 +150,10 @@ def test_adjoint_of_every_system_matches_oracle(case):
     g.adjoint_seed(torch.tensor(w, device="cuda"), lam)
     out = g.adjoint_step(steps, lam, tmp, hist)
     dQ0 = g.adjoint_to_initial(out, Q).cpu().numpy()
-    trk = {"omega_tracker": g.param("omega_tracker")} if g_tau else {}
-    o = oracle.Oracle(oracle_system, lattice, (n, n), g.param("dt"), g.param("dx"), 1.0 / g.param("omega"),
-                      g.param("g_tau") if g_tau else None, params, Q0=g.reference, **trk)
+    kw = parity.scheme(g, dx, dt, tau, g_tau=g_tau)
+    trk = {"omega_tracker": kw["omega_tracker"]} if g_tau else {}
+    o = oracle.Oracle(oracle_system, lattice, (n, n), kw["dt"], kw["dx"], kw["tau"], kw["g_tau"], params,
+                      Q0=kw["Q0"], **trk)
     o.init(Q)
     ohist = []
     o.step(steps, history=ohist)

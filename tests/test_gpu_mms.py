@@ -12,6 +12,9 @@ import pytest
 
 import oracle
 from oracle import mms
+from paper_2607_05668_amd import inputs
+
+import parity
 
 pytestmark = pytest.mark.gpu
 
@@ -78,15 +81,12 @@ def test_forced_path_matches_oracle(storage, tol):
     assert g.steps == steps
     fQn, fSn = mms.euler_paper()
     X, Y = np.meshgrid(np.arange(n) / n, np.arange(n) / n, indexing="xy")
-    o = oracle.Oracle("euler2d", "D2Q5", (n, n), g.param("dt"), g.param("dx"), 1.0 / g.param("omega"), None,
-                      {"gamma": 1.4}, Q0=g.reference)
+    tau_r = 0.2 if storage == "f64" else 5.0
+    c = parity.scheme(g, 1.0 / n, 0.05 / n, 0.5 + tau_r * 0.05 / n)
+    o = oracle.Oracle("euler2d", "D2Q5", (n, n), c["dt"], c["dx"], c["tau"], None, {"gamma": 1.4}, Q0=c["Q0"])
     o.init(fQn(X, Y, 0.0))
     o.step(steps, source=lambda t: fSn(X, Y, t))
-    Qo = o.moments()
-    errs = {"rho": rel(Qg[0], Qo[0]), "m": rel(Qg[1:3], Qo[1:3]), "E": rel(Qg[3], Qo[3])}
-    print("rel L2 vs oracle", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
-    for k, v in errs.items():
-        assert v <= tol, k
+    parity.check_fields({"rho": slice(0, 1), "m": slice(1, 3), "E": slice(3, 4)}, Qg, o.moments(), tol)
 
 
 def test_euler_convergence_study_on_the_gpu():
@@ -344,18 +344,16 @@ def test_hcnsf_forced_path_matches_oracle(storage, tol):
     hcnsf_drive(st, fS, fB, G, steps, real)
     Qg = st.moments().cpu().numpy()
     Xn, Yn, Zn = (a.cpu().numpy() for a in G)
-    o = oracle.Oracle("hcnsf3d_trk14", "D3Q7", (n, n, n), st.param("dt"), st.param("dx"), 1.0 / st.param("omega"),
-                      st.param("g_tau"), dict(zip(("gamma", "mu", "kappa", "eta"), _hc_params())),
-                      Q0=st.reference, omega_tracker=st.param("omega_tracker"))
+    tau_r = 10.0 if storage == "f64" else 20.0
+    c = parity.scheme(st, 1.0 / n, 0.05 / n, 0.5 + tau_r * 0.05 / n, g_tau=inputs.PRESETS["hcnsf256"].g_tau)
+    o = oracle.Oracle("hcnsf3d_trk14", "D3Q7", (n, n, n), c["dt"], c["dx"], c["tau"], c["g_tau"],
+                      dict(zip(("gamma", "mu", "kappa", "eta"), _hc_params())), Q0=c["Q0"],
+                      omega_tracker=c["omega_tracker"])
     rnd = (lambda a: a) if storage == "f64" else (lambda a: a.astype(np.float32).astype(np.float64))
     o.init(Q0.cpu().numpy(), b=rnd(fBn(Xn, Yn, Zn, 0.0)))
     o.step(steps, source=lambda t: rnd(fSn(Xn, Yn, Zn, t)), b=lambda t: rnd(fBn(Xn, Yn, Zn, t)))
     Qo = o.moments()
-    errs = {"rho": rel(Qg[0], Qo[0]), "m": rel(Qg[1:4], Qo[1:4]), "E": rel(Qg[4], Qo[4]),
-            "G": rel(Qg[5:], Qo[5:])}
-    print("rel L2 vs oracle", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
-    for k, v in errs.items():
-        assert v <= tol, k
+    parity.check_fields({"rho": slice(0, 1), "m": slice(1, 4), "E": slice(4, 5), "G": slice(5, None)}, Qg, Qo, tol)
 
 
 def _hc_params():

@@ -14,6 +14,8 @@ import pytest
 import oracle
 from paper_2607_05668_amd import inputs
 
+import parity
+
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
@@ -43,15 +45,18 @@ def rel(a, b):
     return math.sqrt(float(np.sum((a - b) ** 2)) / float(np.sum(b ** 2)))
 
 
-def twin(g, params):
+def twin(g, params, rec, Q0=None):
     """The FP64 oracle running exactly the scheme the stepper runs: the same
     reference state and the parameters in use (with single-precision
-    arithmetic the library rounds dt/dx and 2 - omega once to float)."""
-    g_tau = g.param("g_tau") if "g_tau" in params else None
+    arithmetic the library rounds dt/dx and 2 - omega once to float), each
+    checked first against the recipe values rec = (dx, dt, tau) the test
+    asked for."""
+    g_tau = params.get("g_tau")
     p = {k: v for k, v in params.items() if k != "g_tau"}
-    return oracle.Oracle(g.system, g.lattice, g.shape, g.param("dt"), g.param("dx"), 1.0 / g.param("omega"),
-                         g_tau if g_tau and g_tau > 0 else None, p, Q0=g.reference,
-                         omega_tracker=g.param("omega_tracker") if g_tau and g_tau > 0 else None)
+    dx, dt, tau = rec
+    kw = parity.scheme(g, dx, dt, tau, g_tau=g_tau, Q0=Q0)
+    return oracle.Oracle(g.system, g.lattice, g.shape, kw["dt"], kw["dx"], kw["tau"], kw["g_tau"], p,
+                         Q0=kw["Q0"], omega_tracker=kw.get("omega_tracker"))
 
 
 def _swe_pair(nx, ny, steps, storage="f32", with_b=True, tau_r=2.0, f=0.2):
@@ -71,7 +76,7 @@ def _swe_pair(nx, ny, steps, storage="f32", with_b=True, tau_r=2.0, f=0.2):
     g.init(Q)
     g.step(steps)
     Qg = g.moments().cpu().numpy()
-    o = twin(g, {"g": 1.0})
+    o = twin(g, {"g": 1.0}, (dx, dt, tau), Q0=[1.0, 0.0, 0.0])
     o.init(Q)
     o.step(steps, b=b)
     return Qg, o.moments(), g, o
@@ -82,20 +87,14 @@ def test_swe_fp32_matches_oracle(shape):
     nx, ny = shape
     print(f"swe2d D2Q9 f32 {nx}x{ny} 200 steps", flush=True)
     Qg, Qo, _, _ = _swe_pair(nx, ny, 200)
-    eh, em = rel(Qg[0], Qo[0]), rel(Qg[1:], Qo[1:])
-    print(f"rel L2 h {eh:.3e} hu {em:.3e}")
-    assert eh <= 1e-6
-    assert em <= 1e-6
+    parity.check_fields({"h": 0, "hu": slice(1, 3)}, Qg, Qo, 1e-6)
 
 
 def test_swe_fp32_1000_steps_matches_oracle():
     """The configuration's step count on a grid the oracle runs in seconds."""
     print("swe2d D2Q9 f32 256x256 1000 steps", flush=True)
     Qg, Qo, _, _ = _swe_pair(256, 256, 1000, with_b=False)
-    eh, em = rel(Qg[0], Qo[0]), rel(Qg[1:], Qo[1:])
-    print(f"rel L2 h {eh:.3e} hu {em:.3e}")
-    assert eh <= 1e-6
-    assert em <= 1e-6
+    parity.check_fields({"h": 0, "hu": slice(1, 3)}, Qg, Qo, 1e-6)
 
 
 def test_swe_full_size_full_run_elementwise():
@@ -108,14 +107,11 @@ def test_swe_full_size_full_run_elementwise():
     g.init(Q)
     g.step(p.steps)
     Qg = g.moments().cpu().numpy()
-    o = twin(g, p.params)
+    o = twin(g, p.params, parity.recipe(1024, p.scaling, p.f, p.tau_r), Q0=[1.0, 0.0, 0.0])
     o.init(Q)
     o.step(p.steps)
     Qo = o.moments()
-    eh, em = rel(Qg[0], Qo[0]), rel(Qg[1:], Qo[1:])
-    print(f"rel L2 h {eh:.3e} hu {em:.3e}")
-    assert eh <= 1e-6
-    assert em <= 1e-6
+    parity.check_fields({"h": 0, "hu": slice(1, 3)}, Qg, Qo, 1e-6)
 
 
 def test_swe_full_size_conservation_and_bounds():
@@ -148,12 +144,11 @@ def test_advdiff_fp64_matches_oracle():
     g.init(Q)
     g.step(200)
     Qg = g.moments().cpu().numpy()
-    o = twin(g, dict(p.params, g_tau=p.g_tau))
+    o = twin(g, dict(p.params, g_tau=p.g_tau), parity.recipe(64, p.scaling, p.f, p.tau_r), Q0=[1.0, 0.0, 0.0])
     o.init(Q)
     o.step(200)
     Qo = o.moments()
-    assert rel(Qg[0], Qo[0]) <= 1e-12
-    assert rel(Qg[1:], Qo[1:]) <= 1e-12
+    parity.check_fields({"u": 0, "g": slice(1, 3)}, Qg, Qo, 1e-12)
     ex = inputs.advdiff_exact(64, g.time, 0.1, 0.05, 0.01)
     assert rel(Qg[0] - 1.0, ex[0] - 1.0) == pytest.approx(rel(Qo[0] - 1.0, ex[0] - 1.0), rel=1e-9)
 
@@ -174,14 +169,11 @@ def test_neohooke_matches_oracle(storage, tol):
     g.init(Q)
     g.step(2000)
     Qg = g.moments().cpu().numpy()
-    o = twin(g, p.params)
+    o = twin(g, p.params, parity.recipe(256, p.scaling, p.f, p.tau_r), Q0=[1.0, 0.0, 0.0, 1.0, 0.0, 0.0])
     o.init(Q)
     o.step(2000)
     Qo = o.moments()
-    eF, ev = rel(Qg[:4], Qo[:4]), rel(Qg[4:], Qo[4:])
-    print(f"rel L2 F {eF:.3e} v {ev:.3e}")
-    assert eF <= tol
-    assert ev <= tol
+    parity.check_fields({"F": slice(0, 4), "v": slice(4, 6)}, Qg, Qo, tol)
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16", "f16ne"])
@@ -262,9 +254,7 @@ def test_fp16_initialisation_reproduces_fields(storage):
 def test_swe_f16ne_matches_oracle():
     print("swe2d D2Q9 f16ne 256x256 1000 steps", flush=True)
     Qg, Qo, _, _ = _swe_pair(256, 256, 1000, storage="f16ne", with_b=True)
-    eh, em = rel(Qg[0], Qo[0]), rel(Qg[1:], Qo[1:])
-    print(f"rel L2 h {eh:.3e} hu {em:.3e}")
-    assert eh <= 1e-3 and em <= 1e-3
+    parity.check_fields({"h": 0, "hu": slice(1, 3)}, Qg, Qo, 1e-3)
 
 
 @pytest.mark.parametrize("shape", [(37, 100), (5, 24), (4, 64)])
@@ -275,6 +265,4 @@ def test_swe_f16ne_ragged_tiles_match_oracle(shape):
     ny, nx = shape
     print(f"swe2d D2Q9 f16ne {nx}x{ny} 300 steps", flush=True)
     Qg, Qo, _, _ = _swe_pair(nx, ny, 300, storage="f16ne", with_b=True)
-    eh, em = rel(Qg[0], Qo[0]), rel(Qg[1:], Qo[1:])
-    print(f"rel L2 h {eh:.3e} hu {em:.3e}")
-    assert eh <= 1e-3 and em <= 1e-3
+    parity.check_fields({"h": 0, "hu": slice(1, 3)}, Qg, Qo, 1e-3)

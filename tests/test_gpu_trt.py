@@ -10,6 +10,8 @@ import oracle
 from oracle import mms
 from paper_2607_05668_amd import inputs
 
+import parity
+
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
@@ -25,13 +27,16 @@ def rel(a, b):
     return math.sqrt(float(np.sum((a - b) ** 2)) / float(np.sum(b ** 2)))
 
 
-def twin(g, system, lattice, params, trackers):
+def twin(g, system, lattice, params, trackers, rec):
+    """Oracle with the stepper's rates, each checked first against the recipe
+    rec = (dx, dt, tau) and the magic parameter."""
     phys = {k: v for k, v in params.items() if k not in ("g_tau", "trt_lambda")}
-    kw = {"omega_plus": g.param("omega_plus")}
+    g_tau = params.get("g_tau") if trackers else None
+    c = parity.scheme(g, *rec, g_tau=g_tau, trt_lambda=params["trt_lambda"])
+    kw = {"omega_plus": c["omega_plus"]}
     if trackers:
-        kw.update(omega_tracker=g.param("omega_tracker"), omega_plus_tracker=g.param("omega_plus_tracker"))
-    return oracle.Oracle(system, lattice, g.shape, g.param("dt"), g.param("dx"), 1.0 / g.param("omega"),
-                         g.param("g_tau") if trackers else None, phys, Q0=g.reference, **kw)
+        kw.update(omega_tracker=c["omega_tracker"], omega_plus_tracker=c["omega_plus_tracker"])
+    return oracle.Oracle(system, lattice, g.shape, c["dt"], c["dx"], c["tau"], c["g_tau"], phys, Q0=c["Q0"], **kw)
 
 
 @pytest.mark.parametrize("storage,lattice,shape,tol", [("f32", "D2Q9", (48, 64), 1e-6),
@@ -51,14 +56,11 @@ def test_swe_trt_matches_oracle(storage, lattice, shape, tol):
     g.init(Q)
     g.step(300)
     assert g.param("omega_plus") != pytest.approx(g.param("omega"), rel=1e-3)
-    o = twin(g, "swe2d", lattice, params, False)
+    o = twin(g, "swe2d", lattice, params, False, (dx, dt, 0.5 + 2.0 * dt))
     o.init(Q)
     o.step(300)
     Qg, Qo = g.moments().cpu().numpy(), o.moments()
-    errs = {"h": rel(Qg[0], Qo[0]), "hu": rel(Qg[1:], Qo[1:])}
-    print("rel L2 vs oracle", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
-    for k, v in errs.items():
-        assert v <= tol, k
+    parity.check_fields({"h": slice(0, 1), "hu": slice(1, None)}, Qg, Qo, tol)
 
 
 @pytest.mark.parametrize("storage,tol", [("f32", 1e-6), ("f64", 1e-12)])
@@ -77,14 +79,11 @@ def test_cnsf_trt_with_trackers_matches_oracle(storage, tol):
     Q = fQ(X, Y, 0.0)
     g.init(Q)
     g.step(300)
-    o = twin(g, "cnsf_trk2d", "D2Q5", params, True)
+    o = twin(g, "cnsf_trk2d", "D2Q5", params, True, (dx, dt, 0.5 + 60.0 * dt))
     o.init(Q)
     o.step(300)
     Qg, Qo = g.moments().cpu().numpy(), o.moments()
-    errs = {"rho": rel(Qg[0], Qo[0]), "m": rel(Qg[1:3], Qo[1:3]), "E": rel(Qg[3], Qo[3]), "G": rel(Qg[4:], Qo[4:])}
-    print("rel L2 vs oracle", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
-    for k, v in errs.items():
-        assert v <= tol, k
+    parity.check_fields({"rho": slice(0, 1), "m": slice(1, 3), "E": slice(3, 4), "G": slice(4, None)}, Qg, Qo, tol)
 
 
 def test_hcnsf_trt_matches_oracle():
@@ -102,15 +101,11 @@ def test_hcnsf_trt_matches_oracle():
     g.init(Q)
     g.step(60)
     Bo = g._fields["coef"].cpu().numpy().astype(np.float64).reshape(B.shape)
-    o = twin(g, "hcnsf3d_trk14", "D3Q7", params, True)
+    o = twin(g, "hcnsf3d_trk14", "D3Q7", params, True, (dx, dt, 0.5 + 20.0 * dt))
     o.init(Q, b=Bo)
     o.step(60, b=Bo)
     Qg, Qo = g.moments().cpu().numpy(), o.moments()
-    errs = {"rho": rel(Qg[0], Qo[0]), "m": rel(Qg[1:4], Qo[1:4]), "E": rel(Qg[4], Qo[4]),
-            "G_u": rel(Qg[5:11], Qo[5:11]), "G_T": rel(Qg[11:], Qo[11:])}
-    print("rel L2 vs oracle", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
-    for k, v in errs.items():
-        assert v <= 1e-6, k
+    parity.check_fields({"rho": slice(0, 1), "m": slice(1, 4), "E": slice(4, 5), "G_u": slice(5, 11), "G_T": slice(11, None)}, Qg, Qo, 1e-6)
 
 
 @pytest.mark.parametrize("storage,lattice,tol", [("f32", "D2Q9", 1e-6), ("f64", "D2Q9", 1e-12),
@@ -130,15 +125,13 @@ def test_swe_regularized_matches_oracle(storage, lattice, tol):
     Q = inputs.swe_initial(64)[:, :48, :64]
     g.init(Q)
     g.step(300)
-    o = oracle.Oracle("swe2d", lattice, shape, g.param("dt"), g.param("dx"), 1.0 / g.param("omega"), None,
-                      {"g": 1.0}, Q0=g.reference, regularized=True)
+    c = parity.scheme(g, dx, dt, 0.5 + 20.0 * dt, Q0=[1.0, 0.0, 0.0])
+    o = oracle.Oracle("swe2d", lattice, shape, c["dt"], c["dx"], c["tau"], None, {"g": 1.0}, Q0=c["Q0"],
+                      regularized=True)
     o.init(Q)
     o.step(300)
     Qg, Qo = g.moments().cpu().numpy(), o.moments()
-    errs = {"h": rel(Qg[0], Qo[0]), "hu": rel(Qg[1:], Qo[1:])}
-    print("rel L2 vs oracle", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
-    for k, v in errs.items():
-        assert v <= tol, k
+    parity.check_fields({"h": slice(0, 1), "hu": slice(1, None)}, Qg, Qo, tol)
 
 
 def test_nsf17_regularized_matches_oracle():
@@ -155,13 +148,10 @@ def test_nsf17_regularized_matches_oracle():
     g.init(Q)
     g.step(60)
     phys = {k: pre.params[k] for k in ("gamma", "mu", "kappa")}
-    o = oracle.Oracle("nsf3d_trk17", "D3Q7", (n, n, n), g.param("dt"), g.param("dx"), 1.0 / g.param("omega"),
-                      g.param("g_tau"), phys, Q0=g.reference, omega_tracker=g.param("omega_tracker"),
-                      regularized=True)
+    c = parity.scheme(g, dx, dt, 0.5 + pre.tau_r * dt, g_tau=pre.g_tau, Q0=inputs.NsfMms().reference())
+    o = oracle.Oracle("nsf3d_trk17", "D3Q7", (n, n, n), c["dt"], c["dx"], c["tau"], c["g_tau"], phys, Q0=c["Q0"],
+                      omega_tracker=c["omega_tracker"], regularized=True)
     o.init(Q)
     o.step(60)
     Qg, Qo = g.moments().cpu().numpy(), o.moments()
-    errs = {"rho": rel(Qg[0], Qo[0]), "m": rel(Qg[1:4], Qo[1:4]), "E": rel(Qg[4], Qo[4]), "G": rel(Qg[5:], Qo[5:])}
-    print("rel L2 vs oracle", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
-    for k, v in errs.items():
-        assert v <= 1e-6, k
+    parity.check_fields({"rho": slice(0, 1), "m": slice(1, 4), "E": slice(4, 5), "G": slice(5, None)}, Qg, Qo, 1e-6)

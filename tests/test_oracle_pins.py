@@ -281,9 +281,6 @@ def test_nsf17_flux_matches_printed_hcnsf_expansion():
     temperature trackers equal the printed tracker rows."""
     par = {"gamma": 1.4, "mu": 0.037, "kappa": 0.11}
     tg = 0.0123
-    o = oracle.Oracle("nsf3d_trk17", "D3Q7", (4, 4, 4), 0.001, 0.01, 0.6, None,
-                      dict(par, tau_grad=tg), Q0=np.zeros(17), shifted=False) \
-        if False else None
     o = oracle.Oracle("nsf3d_trk17", "D3Q7", (4, 4, 4), tg / 3.0, 0.01, 0.6, 3.0, par,
                       Q0=inputs.NsfMms().reference())
     assert o.params["tau_grad"] == pytest.approx(tg, rel=1e-15)
@@ -1470,3 +1467,19 @@ def test_hcnsf_mms_at_64():
     for k in ("rho", "m", "E"):
         s = g[f"hcnsf_double_{k}_eoc_L2"]
         assert 2 ** (2 * s - 0.3) < e[k] / g[f"hcnsf_double_{k}_relL2_N256"] < 2 ** (2 * s + 0.3), k
+
+
+def test_compiled_forcing_equals_numpy_evaluation():
+    """The generated-C evaluation of a manufactured forcing (used by the 3D
+    parity tests for speed) gives numpy's values of the same SymPy residual
+    up to rounding order, at random points and times."""
+    m = inputs.NsfMms()
+    _, fS = mms.nsf17(m.gamma, m.rho0, m.p0, m.u0, m.amp, m.mu, m.kappa, 3 * 0.05 / 32)
+    fc = mms.compiled(fS)
+    rng = np.random.default_rng(11)
+    X, Y, Z = (rng.uniform(0, 1, size=(3, 5, 7)) for _ in range(3))
+    for t in (0.0, 0.37, 1.9):
+        a, b = fc(X, Y, Z, t), fS(X, Y, Z, t)
+        assert a.shape == b.shape == (17, 3, 5, 7)
+        assert np.max(np.abs(a - b)) <= 1e-13 * max(1.0, np.max(np.abs(b)))
+        assert np.max(np.abs(b[:5])) > 1e-3 and np.all(b[5:] == 0)
