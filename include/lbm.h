@@ -21,10 +21,15 @@
  * Conventions
  *  - Every device pointer is memory the caller owns (e.g. a torch tensor);
  *    the library never allocates or frees device memory.
- *  - Layouts are structure-of-arrays with x fastest: a field array is
- *    [K][nz][ny][nx], a population array [nz][K][Q][ny][nx] (z-slab major,
- *    so that one slab's populations are contiguous; for 2D grids, nz = 1,
- *    this is [K][Q][ny][nx]).
+ *  - A field array is [K][nz][ny][nx], x fastest.  A population array is
+ *    tile-blocked: the nx*ny cells of each z-slab, in-plane index
+ *    yx = y nx + x, are cut into tiles of 64 consecutive cells, the last
+ *    tile of a slab padded to 64, and a tile holds all K*Q populations of
+ *    its cells, [nz][tiles][K][Q][64]: population (k, i) of cell (x, y, z)
+ *    is element ((z T + yx / 64) K Q + k Q + i) 64 + yx % 64, with
+ *    T = ceil(nx ny / 64) tiles per slab.  A wavefront's 64 cells of one
+ *    population are one contiguous run and all its populations one block.
+ *    Padding elements are never read.
  *  - Population order: D2Q5 = rest, +x, +y, -x, -y; D2Q9 = D2Q5 then
  *    (+1,+1), (-1,+1), (-1,-1), (+1,-1); D3Q7 = rest, +x, -x, +y, -y, +z, -z.
  *  - Calls are asynchronous on the bound HIP stream unless they return host
@@ -144,12 +149,12 @@ int lbm_num_velocities(const lbm_state *h);
  *                   Lambda = (1/omega+ - 1/2)(1/omega- - 1/2): the parts of
  *                   each field's populations antisymmetric under c -> -c
  *                   (which carry the flux) relax at the field's BGK rate
- *                   omega-, the symmetric parts at omega+ (Sec. 2.4 names
+ *                   omega-, the symmetric parts at omega+ (Sec. 2.3 names
  *                   such operators as consuming the same equilibria).  Not
  *                   with LBM_F16NE storage, the moment history or the
  *                   adjoint (LBM_EINVAL).
  *                   regularized (0 or 1; default 0): regularized collision
- *                   (Sec. 2.4, the Latt-Chopard operator with first-order
+ *                   (Sec. 2.3, the Latt-Chopard operator with first-order
  *                   Hermite projection): each field's non-equilibrium part
  *                   is replaced by w_i c_i . Pi1 / cs^2, Pi1 its first
  *                   moment, before relaxing at the field's BGK rate, so
@@ -158,12 +163,23 @@ int lbm_num_velocities(const lbm_state *h);
  *                   drops the symmetric non-equilibrium, which makes it
  *                   unstable near omega -> 2 on some flows.  Excludes
  *                   trt_lambda > 0, LBM_F16NE, the moment history and the
- *                   adjoint (LBM_EINVAL). */
+ *                   adjoint (LBM_EINVAL).
+ *                   check_every (a step count N >= 0, default 0; may be
+ *                   changed at any time): failure detection.  Outside the
+ *                   sub-characteristic bound (Sec. 2.4.2) the scheme blows
+ *                   up; with N > 0, lbm_step and lbm_step_record scan the
+ *                   populations for non-finite values after every step whose
+ *                   count is a multiple of N (one LBM_RED_NONFINITE
+ *                   reduction, which synchronises the stream) and return
+ *                   LBM_ENONFINITE at the first one that finds any; the step
+ *                   counter then stands at that step.
+ *                   check_subchar (0 or 1, default 1): the sub-characteristic
+ *                   check of lbm_init_moments. */
 int lbm_set_param(lbm_state *h, const char *name, double v);
 
 /* Read a parameter in use: "dt", "dx", "lambda" (dt/dx), "tau", "omega"
  * (conserved fields), "omega_tracker", "tau_grad", "g_tau", "g", "t0",
- * "trt_lambda", "regularized", and once bound "omega_plus" /
+ * "trt_lambda", "regularized", "check_every", and once bound "omega_plus" /
  * "omega_plus_tracker" (the
  * symmetric TRT rates; equal to omega / omega_tracker under BGK).  Under TRT
  * the kernels use a = (omega+ + omega-)/2 and b = (omega+ - omega-)/2, in
@@ -198,8 +214,9 @@ int lbm_set_reference(lbm_state *h, const double *Q0);
 int lbm_get_reference(const lbm_state *h, double *Q0_out);
 
 /* Bytes the caller must provide: which = 0 one population buffer
- * (K*Q*cells*sizeof(storage); for LBM_F16NE the binary16 deviations padded
- * to 256 bytes followed by K*cells floats of moments); which = 1 scratch for
+ * (K*Q*nz*ceil(nx ny / 64)*64*sizeof(storage), the tile-blocked layout; for
+ * LBM_F16NE the binary16 deviations [K][Q][cells] padded to 256 bytes
+ * followed by K*cells floats of moments); which = 1 scratch for
  * reductions. */
 size_t lbm_required_bytes(const lbm_state *h, int which);
 
@@ -234,7 +251,9 @@ int lbm_set_field(lbm_state *h, const char *name, const void *dev_ptr);
 int lbm_init_moments(lbm_state *h, const double *Q_dev);
 
 /* Advance n collide-and-stream steps (eq. lbe_update), one fused kernel per
- * step with pull streaming between the A/B buffers.  Asynchronous. */
+ * step with pull streaming between the A/B buffers.  Asynchronous, unless
+ * check_every is set (see lbm_set_param): then LBM_ENONFINITE reports
+ * non-finite populations. */
 int lbm_step(lbm_state *h, int n);
 
 /* Like lbm_step, additionally writing the pre-collision moment deviations
@@ -302,11 +321,11 @@ int lbm_restore(lbm_state *h, const void *dev_buf, long long step);
  *
  * lbm_bw_streams reproduces the memory-access pattern of the 2D D2Q9 step
  * without its arithmetic: src and dst each hold 9 * fields float planes of
- * nx * ny cells ([fields][9][ny][nx], byte size 36 fields nx ny); every
- * cell (x, y) reads plane j at the periodic pull position (x, y) - c_(j mod 9)
- * (D2Q9 order of the population layout) and writes it to plane j at (x, y),
- * one 4-byte element per lane and plane, all loads of a cell issued before
- * its stores.  fields must be 3 or 6; LBM_EINVAL otherwise or for null
+ * nx * ny cells in the tile-blocked population layout ([tiles][9 fields][64],
+ * byte size 36 fields ceil(nx ny / 64) 64); every cell (x, y) reads plane j
+ * at the periodic pull position (x, y) - c_(j mod 9) (D2Q9 order of the
+ * population layout) and writes it to plane j at (x, y), one 4-byte element
+ * per lane and plane, all loads of a cell issued before its stores.  fields must be 3 or 6; LBM_EINVAL otherwise or for null
  * pointers or nx, ny < 1.  Asynchronous on hip_stream.  With the step's
  * own sizes it measures what the memory system delivers for that access
  * pattern. */

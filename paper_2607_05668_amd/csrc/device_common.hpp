@@ -83,24 +83,30 @@ __device__ inline void cell_coords(I cell, int nx, int ny, int &x, int &y, int &
 }
 
 // ------------------------------------------------------- addressing ----
-// Population layout [nz][K][Q][ny][nx]: z-slab major, so that the K Q
-// population planes of one slab are contiguous and a wave's loads and
-// stores touch a few pages instead of K Q planes far apart (the per-CU
-// address-translation cache would otherwise miss).  For 2D grids this is
-// [K][Q][cells].  Element of population (k, i) stored at cell c = z P + yx:
+// Population layout [nz][tiles][K][Q][kTile] (impl.hpp): the cells of a
+// z-slab (P = nx ny, in-plane index yx = y nx + x) are cut into tiles of
+// kTile, the slab padded to whole tiles.  Element offset inside a slab of
+// population (k, i) of in-plane index yx:
+template <int K, int Q, class I>
+__device__ inline I tile_offset(I yx)
+{
+    return (yx / (I)kTile) * (I)(K * Q * kTile) + (yx % (I)kTile);
+}
+// and in the whole buffer, for cell c = z P + yx:
 template <int K, int Q>
 __device__ inline size_t pop_at(int k, int i, long long c, long long P)
 {
     const long long z = c / P;
-    return ((size_t)(z * K + k) * Q + i) * (size_t)P + (size_t)(c - z * P);
+    const long long Pp = (P + kTile - 1) / kTile * kTile;
+    return (size_t)z * K * Q * (size_t)Pp + (size_t)tile_offset<K, Q>(c - z * P) + (size_t)(k * Q + i) * kTile;
 }
 
-// Population buffers are [K][Q][cells].  A thread reaches field k through
-// the wave-uniform base of that field's [Q][cells] block (kept in scalar
-// registers) plus a per-lane byte offset.  When a block is below 4 GiB the
-// offsets and the index arithmetic are 32-bit and every access takes the
-// scalar-base + vector-offset form, with no 64-bit address arithmetic per
-// load or store; larger grids use 64-bit offsets.
+// A thread reaches population (k, i) of a cell through the wave-uniform
+// base of its z-slab shifted by (k Q + i) kTile elements (kept in scalar
+// registers) plus a per-lane byte offset inside the slab.  When a slab is
+// below 4 GiB the offsets and the index arithmetic are 32-bit and every
+// access takes the scalar-base + vector-offset form, with no 64-bit address
+// arithmetic per load or store; larger slabs use 64-bit offsets.
 template <bool O32> struct Index { using T = unsigned long long; };
 template <> struct Index<true> { using T = unsigned; };
 

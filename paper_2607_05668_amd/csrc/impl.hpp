@@ -28,6 +28,14 @@ constexpr int kBlock = LBM_BLOCK;    // threads per workgroup (wave64 multiples)
 // non-temporal stores: MI355X's Infinity Cache holds 256 MiB.
 constexpr size_t kLastLevelCacheBytes = (size_t)256 << 20;
 constexpr int kRedBlocks = 1024;     // workgroups of the first reduction pass
+// Population layout: each z-slab's nx*ny cells are cut into tiles of kTile
+// consecutive cells (x fastest, rows continue into the next tile), and a
+// tile keeps all K*Q populations of its cells together,
+// [z][tile][K][Q][kTile]: one wavefront's 64 cells of one population are one
+// contiguous 256-byte (FP32) run, and all of a wavefront's populations one
+// contiguous block.  The last tile of a slab is padded.
+constexpr int kTile = 64;
+__host__ __device__ inline long long padded_plane(long long P) { return (P + kTile - 1) / kTile * kTile; }
 
 // Manufactured-solution forcing of the 3D NSF system (conserved rows).
 template <class R>
@@ -132,6 +140,10 @@ struct lbm_state_impl {
     double mms_amp = 0.05, mms_rho0 = 1.0, mms_p0 = 1.0, mms_u0 = 0.0;
     double t0 = 0.0;
     int check_subchar = 1;
+    long long check_every = 0;             // non-finite scan every N steps (0: never)
+    int use_graphs = 1;                    // replay runs of small-grid launches from HIP graphs
+    long long epoch = 0;                   // advanced whenever kernel arguments may change
+    void *graphs = nullptr;                // captured launch graphs (lbm_api.cpp)
     double Q0[LBM_MAXK] = {0};
     bool q0_set = false;
     int scale_exp[LBM_MAXK] = {0};

@@ -40,7 +40,8 @@ hipError_t lbm_launch_copy(void *dst, const void *src, size_t n, hipStream_t s)
     return hipGetLastError();
 }
 
-// The D2Q9 step's memory pattern without arithmetic: N = 9 fields planes,
+// The D2Q9 step's memory pattern without arithmetic, in the population
+// layout of the step (tiles of kTile cells holding all N = 9 fields planes):
 // plane j pulled from (x, y) - c_(j mod 9), periodic, and stored at (x, y).
 template <int N>
 __global__ __launch_bounds__(kBlock) void k_streams(const float *__restrict__ src, float *__restrict__ dst, int nx,
@@ -55,16 +56,16 @@ __global__ __launch_bounds__(kBlock) void k_streams(const float *__restrict__ sr
     for (int j = 0; j < N; ++j) {
         const int i = j % 9;
         const unsigned s = (unsigned)wrapi(y - D2Q9::cy[i], ny) * nx + (unsigned)wrapi(x - D2Q9::cx[i], nx);
-        v[j] = *byte_at(src + (size_t)j * P, s * 4u);
+        v[j] = *byte_at(src + (size_t)j * kTile, tile_offset<N, 1>(s) * 4u);
     }
 #pragma unroll
-    for (int j = 0; j < N; ++j) *byte_at(dst + (size_t)j * P, c * 4u) = v[j];
+    for (int j = 0; j < N; ++j) *byte_at(dst + (size_t)j * kTile, tile_offset<N, 1>(c) * 4u) = v[j];
 }
 
 hipError_t lbm_launch_streams(void *dst, const void *src, int nx, int ny, int fields, hipStream_t s)
 {
     const size_t P = (size_t)nx * ny;
-    if (P * 4 > 0xffffffffull) return hipErrorInvalidValue;     // 32-bit byte offsets per plane
+    if (padded_plane((long long)P) * 36 * fields > 0xffffffffull) return hipErrorInvalidValue;   // 32-bit byte offsets
     const dim3 grid((unsigned)((P + kBlock - 1) / kBlock));
     if (fields == 3)
         hipLaunchKernelGGL(k_streams<27>, grid, dim3(kBlock), 0, s, (const float *)src, (float *)dst, nx, ny);

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -181,8 +182,6 @@ size_t arith_bytes(const lbm_state *h) { return h->storage == LBM_F64 ? 8 : 4; }
 
 size_t aux_bytes() { return sizeof(double) * ((size_t)2 * LBM_MAXK * kRedBlocks + 4 * LBM_MAXK); }
 
-double *aux_final(const lbm_state *h) { return (double *)h->aux + (size_t)2 * LBM_MAXK * kRedBlocks; }
-
 int check_ready(lbm_state *h)
 {
     if (!h) return LBM_EINVAL;
@@ -199,6 +198,91 @@ struct SaveHeader {
     int32_t scale_exp[LBM_MAXK];
     uint64_t payload;
 };
+
+// ------------------------------------------------ launch batching ----
+// On small grids a step kernel lasts a few microseconds, about as long as
+// its launch from the host.  There the launches of a run of steps are
+// captured once into a HIP graph (kernel nodes only) and replayed with one
+// call.  A captured launch keeps the arguments it was captured with, so a
+// graph is keyed by everything they depend on: the buffers, the history
+// slice, the A/B parity and a parameter epoch that set_param, set_field,
+// init_moments and load advance.  Kernels whose arguments change from step
+// to step (the in-kernel manufactured forcing reads the time) are never
+// captured; with failure detection on, steps run one by one.
+constexpr long long kGraphMaxCells = 1ll << 20;  // above this a launch is long against its overhead
+constexpr int kGraphMinLaunches = 4;
+constexpr int kGraphChunk = 64;                   // launches per graph
+constexpr size_t kGraphCacheSize = 16;
+
+struct GraphKey {
+    int kind, len, cur;
+    long long epoch;
+    const void *p[4];
+    bool operator==(const GraphKey &o) const
+    {
+        return kind == o.kind && len == o.len && cur == o.cur && epoch == o.epoch && p[0] == o.p[0] &&
+               p[1] == o.p[1] && p[2] == o.p[2] && p[3] == o.p[3];
+    }
+};
+
+struct GraphCache {
+    hipStream_t capture = nullptr;                   // private stream, default priority, used only to capture
+    std::vector<std::pair<GraphKey, hipGraphExec_t>> entries;   // oldest first
+    ~GraphCache()
+    {
+        for (auto &e : entries) (void)hipGraphExecDestroy(e.second);
+        if (capture) (void)hipStreamDestroy(capture);
+    }
+};
+
+GraphCache &graphs(lbm_state *h)
+{
+    if (!h->graphs) h->graphs = new GraphCache();
+    return *(GraphCache *)h->graphs;
+}
+
+bool batch_launches(const lbm_state *h, int n)
+{
+    return h->use_graphs && n >= kGraphMinLaunches && h->C <= kGraphMaxCells &&
+           !(h->sys == SYS_NSF17 && h->mms_on) && h->check_every == 0;
+}
+
+// Replay the graph of `key`, capturing it first with enqueue(stream) if it
+// is not cached.
+template <class F>
+int replay(lbm_state *h, const GraphKey &key, F &&enqueue)
+{
+    GraphCache &gc = graphs(h);
+    hipGraphExec_t exec = nullptr;
+    for (auto &e : gc.entries)
+        if (e.first == key) exec = e.second;
+    hipError_t e;
+    if (!exec) {
+        if (!gc.capture) {
+            e = hipStreamCreateWithFlags(&gc.capture, hipStreamNonBlocking);
+            if (e != hipSuccess) return hipfail(h, e, "graph stream");
+        }
+        e = hipStreamBeginCapture(gc.capture, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hipfail(h, e, "graph capture");
+        const hipError_t le = enqueue(gc.capture);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(gc.capture, &graph);
+        if (le != hipSuccess || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return hipfail(h, le != hipSuccess ? le : e, "graph capture");
+        }
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return hipfail(h, e, "graph instantiate");
+        if (gc.entries.size() >= kGraphCacheSize) {
+            (void)hipGraphExecDestroy(gc.entries.front().second);
+            gc.entries.erase(gc.entries.begin());
+        }
+        gc.entries.emplace_back(key, exec);
+    }
+    e = hipGraphLaunch(exec, h->stream);
+    return e == hipSuccess ? LBM_OK : hipfail(h, e, "graph launch");
+}
 
 }  // namespace
 
@@ -272,6 +356,12 @@ int lbm_set_param(lbm_state *h, const char *name, double v)
     if (!h || !name) return LBM_EINVAL;
     if (!std::isfinite(v)) return fail(h, LBM_EINVAL, "parameter value is not finite");
     const std::string n(name);
+    h->epoch += 1;                      // captured launches may hold the old value
+    if (n == "graphs") {
+        if (v != 0.0 && v != 1.0) return fail(h, LBM_EINVAL, "graphs is 0 or 1");
+        h->use_graphs = v != 0.0;
+        return LBM_OK;
+    }
     if (n == "t0") { h->t0 = v; return LBM_OK; }
     if (n == "regularized") {
         if (h->bound) return fail(h, LBM_EINVAL, "parameters are fixed once bound");
@@ -286,6 +376,11 @@ int lbm_set_param(lbm_state *h, const char *name, double v)
         return LBM_OK;
     }
     if (n == "check_subchar") { h->check_subchar = v != 0.0; return LBM_OK; }
+    if (n == "check_every") {
+        if (!(v >= 0) || v != std::floor(v) || v > 1e15) return fail(h, LBM_EINVAL, "check_every is a step count >= 0");
+        h->check_every = (long long)v;
+        return LBM_OK;
+    }
     if (h->bound && n != "mms") return fail(h, LBM_EINVAL, "parameters are fixed once bound");
     if (h->sys >= SYS_GEN0) {
         const int g = h->sys - SYS_GEN0;
@@ -457,6 +552,8 @@ int lbm_get_param(const lbm_state *h, const char *name, double *v)
     else if (n == "g_tau") *v = h->g_tau;
     else if (n == "g") *v = h->g;
     else if (n == "t0") *v = h->t0;
+    else if (n == "check_every") *v = (double)h->check_every;
+    else if (n == "graphs") *v = h->use_graphs ? 1.0 : 0.0;
     else return LBM_EINVAL;
     return LBM_OK;
 }
@@ -500,8 +597,9 @@ size_t lbm_required_bytes(const lbm_state *h, int which)
     if (which == 0) {
         if (h->storage == LBM_F16NE)   // binary16 deviations, padded, then FP32 moments
             return ((((size_t)h->K * h->Q * (size_t)h->C * 2) + 255) & ~(size_t)255) + (size_t)h->K * h->C * 4;
+        // tile-blocked [nz][tiles][K][Q][kTile], each slab padded to whole tiles
         const size_t s = h->storage == LBM_F64 ? 8 : (h->storage == LBM_F32 ? 4 : 2);
-        return (size_t)h->K * h->Q * (size_t)h->C * s;
+        return (size_t)h->K * h->Q * (size_t)padded_plane((long long)h->nx * h->ny) * (size_t)h->nz * s;
     }
     if (which == 1) return aux_bytes();
     return 0;
@@ -575,6 +673,7 @@ int lbm_bind(lbm_state *h, void *pop_a, void *pop_b, void *aux, void *hip_stream
 int lbm_set_field(lbm_state *h, const char *name, const void *dev_ptr)
 {
     if (!h || !name) return LBM_EINVAL;
+    h->epoch += 1;
     if (h->sys == SYS_SWE && !std::strcmp(name, "grad_zb")) {
         h->field_b = dev_ptr;
         return LBM_OK;
@@ -620,6 +719,7 @@ int lbm_init_moments(lbm_state *h, const double *Q_dev)
     }
     h->cur = 0;
     h->nsteps = 0;
+    h->epoch += 1;                      // the F16 scales may have changed
     e = h->L->init(*h, Q_dev, h->pop[0], h->stream);
     if (e != hipSuccess) return hipfail(h, e, "init");
     if (h->check_subchar) {
@@ -636,18 +736,59 @@ int lbm_init_moments(lbm_state *h, const double *Q_dev)
     return LBM_OK;
 }
 
+// Failure detection (Sec. 2.4.2: outside the sub-characteristic bound the
+// scheme blows up): with check_every = N > 0, after every step whose count
+// is a multiple of N the populations are scanned for non-finite values (the
+// LBM_RED_NONFINITE reduction, which synchronises) and stepping stops there.
+static int check_finite(lbm_state *h)
+{
+    double cnt = 0.0;
+    const int rc = lbm_reduce(h, LBM_RED_NONFINITE, nullptr, &cnt);
+    if (rc) return rc;
+    if (cnt != 0.0) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "%.0f non-finite populations after step %lld", cnt, h->nsteps);
+        return fail(h, LBM_ENONFINITE, buf);
+    }
+    return LBM_OK;
+}
+
 static int run_steps(lbm_state *h, int n, void *qhist)
 {
     int rc = check_ready(h);
     if (rc) return rc;
     if (n < 0) return fail(h, LBM_EINVAL, "negative step count");
     const size_t stride = (size_t)h->K * (size_t)h->C * arith_bytes(h);
-    for (int j = 0; j < n; ++j) {
+    int j = 0;
+    if (batch_launches(h, n)) {
+        for (int len; (len = std::min(kGraphChunk, n - j)) >= kGraphMinLaunches; j += len) {
+            char *q0 = qhist ? (char *)qhist + (size_t)j * stride : nullptr;
+            const GraphKey key = {0, len, h->cur, h->epoch, {h->pop[0], h->pop[1], q0, nullptr}};
+            const int cur0 = h->cur;
+            rc = replay(h, key, [&](hipStream_t s) {
+                int c = cur0;
+                for (int i = 0; i < len; ++i) {
+                    const hipError_t e = h->L->step(*h, h->pop[c], h->pop[c ^ 1], q0 ? q0 + (size_t)i * stride : nullptr, s);
+                    if (e != hipSuccess) return e;
+                    c ^= 1;
+                }
+                return hipSuccess;
+            });
+            if (rc) return rc;
+            h->cur ^= len & 1;
+            h->nsteps += len;
+        }
+    }
+    for (; j < n; ++j) {
         void *q = qhist ? (char *)qhist + (size_t)j * stride : nullptr;
         const hipError_t e = h->L->step(*h, h->pop[h->cur], h->pop[h->cur ^ 1], q, h->stream);
         if (e != hipSuccess) return hipfail(h, e, "step");
         h->cur ^= 1;
         h->nsteps += 1;
+        if (h->check_every > 0 && h->nsteps % h->check_every == 0) {
+            rc = check_finite(h);
+            if (rc) return rc;
+        }
     }
     return LBM_OK;
 }
@@ -672,17 +813,20 @@ int lbm_moments(lbm_state *h, void *Q_out_dev, int absolute, int out_dtype)
     return e == hipSuccess ? LBM_OK : hipfail(h, e, "moments");
 }
 
-int lbm_reduce(lbm_state *h, int what, const double *ref_dev, double *host_out)
+// The two reduction passes with workspace ws: partial results of the first
+// pass ([slot][block]) and the final slots after them.
+static int reduce_with(lbm_state *h, int what, const double *ref_dev, double *host_out, double *ws)
 {
     int rc = check_ready(h);
     if (rc) return rc;
     if (!host_out || what < LBM_RED_SUMS || what > LBM_RED_NONFINITE) return fail(h, LBM_EINVAL, "bad reduction");
     if ((what == LBM_RED_RELL2 || what == LBM_RED_RELLINF) && !ref_dev) return fail(h, LBM_EINVAL, "reference field required");
-    hipError_t e = h->L->reduce(*h, h->pop[h->cur], what, ref_dev, (double *)h->aux, h->stream);
+    hipError_t e = h->L->reduce(*h, h->pop[h->cur], what, ref_dev, ws, h->stream);
     if (e != hipSuccess) return hipfail(h, e, "reduce");
     const int nslot = (what == LBM_RED_MAXSPEED || what == LBM_RED_NONFINITE) ? 1 : (what == LBM_RED_SUMS ? h->K : 2 * h->K);
     double r[2 * LBM_MAXK];
-    e = hipMemcpyAsync(r, aux_final(h), nslot * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    e = hipMemcpyAsync(r, ws + (size_t)2 * LBM_MAXK * kRedBlocks, nslot * sizeof(double), hipMemcpyDeviceToHost,
+                       h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hipfail(h, e, "reduce copy");
     switch (what) {
@@ -704,6 +848,11 @@ int lbm_reduce(lbm_state *h, int what, const double *ref_dev, double *host_out)
         break;
     }
     return LBM_OK;
+}
+
+int lbm_reduce(lbm_state *h, int what, const double *ref_dev, double *host_out)
+{
+    return reduce_with(h, what, ref_dev, host_out, h ? (double *)h->aux : nullptr);
 }
 
 long long lbm_step_count(const lbm_state *h) { return h ? h->nsteps : 0; }
@@ -730,7 +879,26 @@ int lbm_adjoint_step(lbm_state *h, int n, void *lam_a, void *lam_b, const void *
     if (grad_field_dev && !h->field_b) return fail(h, LBM_EINVAL, "no source field attached");
     const size_t stride = (size_t)h->K * (size_t)h->C * arith_bytes(h);
     void *in = lam_a, *out = lam_b;
-    for (int j = n - 1; j >= 0; --j) {
+    int j = n - 1;                       // next history slice, taken in reverse
+    if (batch_launches(h, n)) {
+        for (int len; (len = std::min(kGraphChunk, j + 1)) >= kGraphMinLaunches; j -= len) {
+            const char *qtop = (const char *)Q_hist_dev + (size_t)j * stride;
+            const GraphKey key = {1, len, 0, h->epoch, {in, out, qtop, grad_field_dev}};
+            void *a = in, *b = out;
+            rc = replay(h, key, [&](hipStream_t s) {
+                void *x = a, *y = b;
+                for (int i = 0; i < len; ++i) {
+                    const hipError_t e = h->L->adj_step(*h, x, y, qtop - (size_t)i * stride, grad_field_dev, s);
+                    if (e != hipSuccess) return e;
+                    std::swap(x, y);
+                }
+                return hipSuccess;
+            });
+            if (rc) return rc;
+            if (len & 1) std::swap(in, out);
+        }
+    }
+    for (; j >= 0; --j) {
         const hipError_t e = h->L->adj_step(*h, in, out, (const char *)Q_hist_dev + (size_t)j * stride, grad_field_dev,
                                             h->stream);
         if (e != hipSuccess) return hipfail(h, e, "adjoint_step");
@@ -810,6 +978,7 @@ int lbm_load(lbm_state *h, const void *host_buf, size_t n)
     for (int k = 0; k < h->K; ++k)
         if (hd.Q0[k] != h->Q0[k]) return fail(h, LBM_EINVAL, "checkpoint reference state differs");
     for (int k = 0; k < LBM_MAXK; ++k) h->scale_exp[k] = hd.scale_exp[k];
+    h->epoch += 1;
     h->nsteps = hd.nsteps;
     h->t0 = hd.t0;
     h->cur = 0;
@@ -851,6 +1020,10 @@ int lbm_bw_streams(void *dst, const void *src, int nx, int ny, int fields, void 
     return lbm_launch_streams(dst, src, nx, ny, fields, (hipStream_t)hip_stream) == hipSuccess ? LBM_OK : LBM_EHIP;
 }
 
-void lbm_destroy(lbm_state *h) { delete h; }
+void lbm_destroy(lbm_state *h)
+{
+    if (h && h->graphs) delete (GraphCache *)h->graphs;
+    delete h;
+}
 
 }  // extern "C"

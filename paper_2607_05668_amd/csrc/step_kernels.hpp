@@ -178,25 +178,25 @@ __global__ __launch_bounds__((step_block<Sys, St>())) void k_step(const St *__re
     if (yx >= P) return;
     const I cell = (I)z * P + yx;
     const int y = (int)(yx / (I)p.nx), x = (int)(yx - (I)y * (I)p.nx);
-    // byte offsets inside one (slab, field) block [Q][ny][nx]: the pulled
-    // population i comes from in-plane index src and slab zs
+    // byte offsets inside a slab of the tile-blocked layout: the pulled
+    // population i comes from in-plane index ys nx + xs of slab zs
     I src[Q];
     int zs[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int xs = wrapi(x - Lat::cx[i], p.nx), ys = wrapi(y - Lat::cy[i], p.ny);
         zs[i] = D == 3 ? wrapi(z - Lat::cz[i], p.nz) : 0;
-        src[i] = ((I)i * P + (I)ys * (I)p.nx + (I)xs) * S;
+        src[i] = tile_offset<K, Q>((I)ys * (I)p.nx + (I)xs) * S;
     }
-    const I own = yx * S;
-    const size_t blk = (size_t)Q * (size_t)P;     // elements per (slab, field) block
+    const I own = tile_offset<K, Q>(yx) * S;
+    const size_t slab = (size_t)K * Q * (size_t)((P + kTile - 1) / kTile * kTile);   // elements per z-slab
 
     R f[K][Q];
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const R v = Store<St>::ld(byte_at(fin + ((size_t)zs[i] * K + k) * blk, src[i]));
+            const R v = Store<St>::ld(byte_at(fin + (size_t)zs[i] * slab + (size_t)(k * Q + i) * kTile, src[i]));
             if constexpr (std::is_same<St, _Float16>::value)
                 f[k][i] = v * (R)p.inv_scale[k];
             else
@@ -267,8 +267,13 @@ __global__ __launch_bounds__((step_block<Sys, St>())) void k_step(const St *__re
     }
     if constexpr (Sys::id == SYS_NSF17) {
         if (p.mms.on) {
+            // the manufactured fields are periodic on the unit cube: the
+            // coordinates enter reduced to [0, 1), so the sine arguments stay
+            // below 2 pi on any grid (on the unit grid nothing changes)
+            auto unit = [](R v) { return v - floor(v); };
             R S5[5];
-            nsf_mms_source<R>(p.mms, p.phys, x * p.mms.dx, y * p.mms.dx, z * p.mms.dx, S5);
+            nsf_mms_source<R>(p.mms, p.phys, unit((R)x * p.mms.dx), unit((R)y * p.mms.dx), unit((R)z * p.mms.dx),
+                              S5);
 #pragma unroll
             for (int k = 0; k < 5; ++k) Sk[k] += S5[k];
         }
@@ -367,7 +372,7 @@ __global__ __launch_bounds__((step_block<Sys, St>())) void k_step(const St *__re
             } else {
                 post = fma(c1, eh[i] - fi, eh[i]) + s[i];
             }
-            St *dst = byte_at(fout + ((size_t)z * K + k) * blk, (I)i * P * S + own);
+            St *dst = byte_at(fout + (size_t)z * slab + (size_t)(k * Q + i) * kTile, own);
             if constexpr (std::is_same<St, _Float16>::value) {
                 const _Float16 hv = (_Float16)(post * (R)p.scale[k]);
                 st_pop<NT>(dst, hv);
@@ -379,7 +384,7 @@ __global__ __launch_bounds__((step_block<Sys, St>())) void k_step(const St *__re
         }
         R rest = f[k][0] + acc;
         if constexpr (std::is_same<St, _Float16>::value) rest *= (R)p.scale[k];
-        Store<St>::template st<NT>(byte_at(fout + ((size_t)z * K + k) * blk, own), rest);
+        Store<St>::template st<NT>(byte_at(fout + (size_t)z * slab + (size_t)(k * Q) * kTile, own), rest);
     }
     if constexpr (REC) {
 #pragma unroll
@@ -507,10 +512,13 @@ __global__ __launch_bounds__(kBlock) void k_reduce1(const St *__restrict__ fin, 
     __shared__ double sh[kBlock / 64];
     const size_t C = (size_t)p.C;
     const unsigned nb = gridDim.x;
-    if (what == 4) {   // non-finite populations
+    if (what == 4) {   // non-finite populations (the padding of a slab's last tile is not read)
         double cnt = 0.0;
-        const size_t n = (size_t)K * Q * C;
+        const size_t P = (size_t)p.nx * p.ny, slab = (size_t)K * Q * (size_t)padded_plane((long long)P);
+        const size_t n = slab * p.nz;
         for (size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (size_t)nb * kBlock) {
+            const size_t r = j % slab;
+            if ((r / ((size_t)K * Q * kTile)) * kTile + r % kTile >= P) continue;
             const double v = (double)Store<St>::ld(fin + j);
             cnt += isfinite(v) ? 0.0 : 1.0;
         }
@@ -753,9 +761,9 @@ struct Impl {
     static void launch_step(const lbm_state_impl &h, const void *fin, void *fout, void *qhist, hipStream_t s,
                             const KParams<R> &p)
     {
-        // the 32-bit form needs one (slab, field) block and the history and
-        // source planes below 4 GiB
-        if (fits_o32((long long)h.nx * h.ny, Lat::Q, sizeof(St)) && fits_o32(h.C, 1, sizeof(R)))
+        // the 32-bit form needs one z-slab of populations and the history
+        // and source planes below 4 GiB
+        if (fits_o32(padded_plane((long long)h.nx * h.ny), Sys::K * Lat::Q, sizeof(St)) && fits_o32(h.C, 1, sizeof(R)))
             launch_step<REC, NT, true, COLL>(h, fin, fout, qhist, s, p);
         else
             launch_step<REC, NT, false, COLL>(h, fin, fout, qhist, s, p);

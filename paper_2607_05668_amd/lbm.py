@@ -229,7 +229,8 @@ class Stepper:
         return out
 
     def reduce(self, what, ref=None):
-        out = np.zeros(2 * 17)
+        """FP64 reduction (lbm_reduce)."""
+        out = np.zeros(2 * 18)
         rp = None
         if ref is not None:
             ref = self._field_tensor(ref, self.torch.float64, self.K)
@@ -300,7 +301,7 @@ def bw_streams(dst, src, nx, ny, fields, stream=None):
     at the lattice offsets and stored (no arithmetic); see include/lbm.h."""
     lib = load_library()
     torch = _torch()
-    need = 36 * fields * nx * ny
+    need = 36 * fields * ((nx * ny + 63) // 64 * 64)       # tile-blocked, padded to 64 cells
     if dst.numel() * dst.element_size() < need or src.numel() * src.element_size() < need:
         raise ValueError(f"bw_streams needs {need} bytes per buffer")
     s = stream or torch.cuda.current_stream()

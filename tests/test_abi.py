@@ -49,6 +49,10 @@ def test_create_validates_arguments():
     assert lib.lbm_set_storage(h, lbm.F16) == 0
     assert lib.lbm_required_bytes(h, 0) == 3 * 9 * 64 * 32 * 2
     assert lib.lbm_set_storage(h, 7) == lbm.LBM_EINVAL
+    # tile-blocked layout: each z-slab padded to whole tiles of 64 cells
+    r = ctypes.c_void_p(lib.lbm_create(b"nsf3d_trk17", b"D3Q7", 50, 37, 3, 0.6, 1e-3, 1e-2))
+    assert lib.lbm_required_bytes(r, 0) == 17 * 7 * 3 * (50 * 37 + 6) * 4
+    lib.lbm_destroy(r)
     assert lib.lbm_set_param(h, b"g", 9.81) == 0
     assert lib.lbm_set_param(h, b"mu", 1.0) == lbm.LBM_EINVAL
     assert b"unknown parameter" in lib.lbm_last_error(h)
@@ -188,3 +192,16 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(lbm, "_lib", None)
     with pytest.raises(ImportError, match="not built"):
         lbm.load_library()
+
+
+def test_check_every_host_checks():
+    """Failure-detection interval: a non-negative whole step count, readable
+    back."""
+    lib = lbm.load_library()
+    h = ctypes.c_void_p(lib.lbm_create(b"swe2d", b"D2Q9", 64, 64, 1, 0.6, 1e-3, 1e-2))
+    assert lib.lbm_set_param(h, b"check_every", -1.0) == lbm.LBM_EINVAL
+    assert lib.lbm_set_param(h, b"check_every", 2.5) == lbm.LBM_EINVAL
+    assert lib.lbm_set_param(h, b"check_every", 5.0) == 0
+    v = ctypes.c_double()
+    assert lib.lbm_get_param(h, b"check_every", ctypes.byref(v)) == 0 and v.value == 5.0
+    lib.lbm_destroy(h)

@@ -15,17 +15,38 @@ CX = [0, 1, 0, -1, 0, 1, -1, -1, 1]
 CY = [0, 0, 1, 0, -1, 1, 1, -1, -1]
 
 
-@pytest.mark.parametrize("shape,fields", [((48, 70), 3), ((17, 256), 6)])
+def _to_tiles(planes):
+    """[N, ny, nx] -> the tile-blocked layout [tiles][N][64] of the
+    population buffers (cells y nx + x cut into tiles of 64, last one padded
+    with NaN)."""
+    N = planes.shape[0]
+    P = planes.shape[1] * planes.shape[2]
+    T = (P + 63) // 64
+    flat = np.full((N, T * 64), np.nan, dtype=np.float32)
+    flat[:, :P] = planes.reshape(N, P)
+    return np.ascontiguousarray(flat.reshape(N, T, 64).transpose(1, 0, 2)).ravel()
+
+
+def _from_tiles(buf, N, ny, nx):
+    T = (ny * nx + 63) // 64
+    return buf.reshape(T, N, 64).transpose(1, 0, 2).reshape(N, T * 64)[:, :ny * nx].reshape(N, ny, nx)
+
+
+@pytest.mark.parametrize("shape,fields", [((48, 70), 3), ((17, 256), 6), ((5, 13), 3)])
 def test_streams_probe_is_the_d2q9_pull(shape, fields):
+    """The pattern probe pulls every plane at the D2Q9 offsets in the step's
+    tile-blocked layout (ragged last tile included) and never reads padding."""
     ny, nx = shape
-    src = torch.randn(9 * fields, ny, nx, device="cuda")
+    N = 9 * fields
+    planes = np.random.default_rng(3).normal(size=(N, ny, nx)).astype(np.float32)
+    src = torch.tensor(_to_tiles(planes), device="cuda")
     dst = torch.full_like(src, float("nan"))
     lbm.bw_streams(dst, src, nx, ny, fields)
     torch.cuda.synchronize()
-    s, d = src.cpu().numpy(), dst.cpu().numpy()
-    for j in range(9 * fields):
+    d = _from_tiles(dst.cpu().numpy(), N, ny, nx)
+    for j in range(N):
         i = j % 9
-        assert np.array_equal(d[j], np.roll(s[j], (CY[i], CX[i]), axis=(0, 1))), j
+        assert np.array_equal(d[j], np.roll(planes[j], (CY[i], CX[i]), axis=(0, 1))), j
 
 
 def test_copy_probe_copies_with_a_ragged_tail():
