@@ -1,7 +1,7 @@
 """Conservation law -> collide-and-stream scheme: a host-side compiler slice.
 
 The paper derives its lattice Boltzmann schemes from a declared
-conservation law (Sec. 2.6, Alg. 1): a Buckingham-Pi projection reads the
+conservation law (Sec. 2.5, Alg. 1): a Buckingham-Pi projection reads the
 lattice scaling of every quantity off its SI dimension, *Split* sends the
 terms under a divergence to the flux and the rest to the source, *Cascade*
 replaces every spatial gradient in a flux or source by a gradient tracker
@@ -195,6 +195,7 @@ class Scheme:
     inv_tau_grad: sp.Symbol
     pq: dict                         # field / parameter name -> (p, q)
     parents: dict = field(default_factory=dict)   # tracker name -> parent expression
+    dims: dict = field(default_factory=dict)      # field / parameter name -> SI dimension (Dim)
 
     @property
     def K(self):
@@ -222,6 +223,8 @@ class Model:
         self.laws: list[Terms] = []
         self.velocity = None
         self.tracked_exprs: dict = {}   # symbol -> derived expression tracked as an auxiliary field
+        self.tracked_dims: dict = {}    # symbol -> its SI dimension, when declared
+        self.tracked_vectors: dict = {} # name -> component symbols of a tracked vector
         self.tau_grad = sp.Symbol("tau_grad", positive=True)
 
     def state(self, name, dim: Dim, rank: int = 0):
@@ -247,17 +250,23 @@ class Model:
     def tracker_velocity(self, u):
         self.velocity = u
 
-    def tracked(self, name, expr):
+    def tracked(self, name, expr, dim: Dim = None):
         """A derived quantity whose gradient is tracked directly (instead of
         expanded over the conserved states by the chain rule): returns the
-        symbol(s) to use in the laws; they stand for ``expr`` everywhere."""
+        symbol(s) to use in the laws; they stand for ``expr`` everywhere.
+        ``dim`` (its SI dimension) gives its trackers their lattice scaling."""
         if isinstance(expr, sp.MatrixBase):
             syms = [sp.Symbol(f"{name}{a}", real=True) for a in range(expr.shape[0])]
             for sy, e in zip(syms, expr):
                 self.tracked_exprs[sy] = e
+                if dim is not None:
+                    self.tracked_dims[sy] = dim
+            self.tracked_vectors[name] = syms
             return sp.Matrix(syms)
         sy = sp.Symbol(name, real=True)
         self.tracked_exprs[sy] = expr
+        if dim is not None:
+            self.tracked_dims[sy] = dim
         return sy
 
     # ---- passes ---------------------------------------------------------
@@ -288,7 +297,12 @@ class Model:
             raise ValueError(f"no law for {missing}")
         return order, out
 
-    def compile(self, references=(DENSITY, GAS_CONSTANT)):
+    def compile(self, references=(DENSITY, GAS_CONSTANT), strain=None):
+        """Run Split, Cascade and Assemble.  references: the characteristic
+        reference quantities of the Buckingham-Pi step; strain: the name of
+        a tracked velocity whose gradient enters only through its symmetric
+        part, to be carried by D(D+1)/2 strain trackers (Alg. 1's optional
+        strain reduction)."""
         D = self.dim
         order, split = self._split()
         state_set = set(order)
@@ -346,6 +360,9 @@ class Model:
         rank = {v: i for i, v in enumerate(parents_order)}
         tracker_parents = sorted(trackers, key=lambda v: rank.get(v, len(rank) + list(trackers).index(v)))
         fields = list(order) + [g for v in tracker_parents for g in trackers[v]]
+        names = {}
+        if strain is not None:
+            fields, flux, source, names = _strain_reduce(self, strain, trackers, fields, flux, source, itg, D)
         subs = dict(tracked_syms)
         subs[self.tau_grad] = 1 / itg
         F = [[sp.sympify(e).subs(subs) for e in flux[f]] for f in fields]
@@ -358,13 +375,128 @@ class Model:
                 pq[str(sy)] = pq_of(q.dim)
         for q in self.parameters:
             pq[q.name] = pq_of(q.dim)
+        dims = {}
+        for q in self.states:
+            for sy in q.symbols:
+                dims[str(sy)] = q.dim
+        for q in self.parameters:
+            dims[q.name] = q.dim
         for v in tracker_parents:
-            base = pq.get(str(v))
+            parent_dim = dims.get(str(v)) if v in state_set else self.tracked_dims.get(v)
+            base = None if parent_dim is None else pq_of(parent_dim)
             for g in trackers[v]:
                 pq[str(g)] = None if base is None else (base[0] - 1, base[1])
+                if parent_dim is not None:
+                    dims[str(g)] = parent_dim / LENGTH
+        for f in fields:                   # strain trackers: the parent velocity's gradient
+            if str(f) in names:
+                pdim = self.tracked_dims.get(names[str(f)])
+                pq[str(f)] = None if pdim is None else pq_of(pdim / LENGTH)
+                if pdim is not None:
+                    dims[str(f)] = pdim / LENGTH
         return Scheme(self.name, D, fields, [str(f) for f in fields], len(order), F, S,
                       [q.symbols[0] for q in self.parameters], [q.name for q in self.parameters], itg, pq,
-                      {str(v): parent_expr[v] for v in tracker_parents})
+                      {str(v): parent_expr[v] for v in tracker_parents}, dims)
+
+
+def _strain_reduce(model, name, trackers, fields, flux, source, itg, D):
+    """Alg. 1's optional strain reduction.  The velocity-gradient trackers
+    G_ab (gradient of the tracked vector ``name``, d_b u_a) are replaced by
+    the strain trackers S_ab = (G_ab + G_ba)/2, a <= b, provided every other
+    flux and source depends on G only through its symmetric part: with
+    G_ab = S_ab + W_ab, W antisymmetric, nothing may depend on W.  The
+    trackers' own laws are linear in G with the common advection velocity,
+    so the symmetrised laws close over S: flux (Phi_G_ab + Phi_G_ba)/2,
+    source (S_G_ab + S_G_ba)/2.  Order (00, 11, 22, 01, 02, 12) in 3D,
+    (00, 11, 01) in 2D.  Returns the new (fields, flux, source, strain name
+    -> parent symbol)."""
+    if name not in model.tracked_vectors:
+        raise ValueError(f"strain reduction needs the tracked vector '{name}'")
+    comps = model.tracked_vectors[name]
+    G = [[trackers[comps[a]][b] if comps[a] in trackers else None for b in range(D)] for a in range(D)]
+    if any(g is None for row in G for g in row):
+        raise ValueError(f"the gradient of '{name}' is not tracked in full")
+    pairs = [(a, a) for a in range(D)] + [(a, b) for a in range(D) for b in range(a + 1, D)]
+    Ssym = {(a, b): sp.Symbol(f"S_{name}_{a}{b}", real=True) for a, b in pairs}
+    W = {(a, b): sp.Symbol(f"W_{name}_{a}{b}", real=True) for a, b in pairs if a != b}
+    rep = {}
+    for a in range(D):
+        for b in range(D):
+            if a == b:
+                rep[G[a][b]] = Ssym[(a, a)]
+            elif a < b:
+                rep[G[a][b]] = Ssym[(a, b)] + W[(a, b)]
+            else:
+                rep[G[a][b]] = Ssym[(b, a)] - W[(b, a)]
+    gset = set(rep)
+
+    def sym_only(e, what):
+        r = sp.expand(sp.sympify(e).xreplace(rep))
+        if r.free_symbols & set(W.values()):
+            raise ValueError(f"{what} depends on the antisymmetric part of grad {name}: no strain reduction")
+        return r
+    nflux, nsource = {}, {}
+    for f in fields:
+        if f in gset:
+            continue
+        nflux[f] = [sym_only(e, f"the flux of {f}") for e in flux[f]]
+        nsource[f] = sym_only(source[f], f"the source of {f}")
+    names = {}
+    for a, b in pairs:
+        g1, g2 = G[a][b], G[b][a]
+        sab = Ssym[(a, b)]
+        nflux[sab] = [sym_only((flux[g1][c] + flux[g2][c]) / 2, f"the strain tracker {sab}") for c in range(D)]
+        nsource[sab] = sym_only((sp.sympify(source[g1]) + source[g2]) / 2, f"the strain tracker {sab}")
+        names[str(sab)] = comps[a]
+    first = min(i for i, f in enumerate(fields) if f in gset)
+    rest = [f for f in fields if f not in gset]
+    nfields = rest[:first] + [Ssym[pr] for pr in pairs] + rest[first:]
+    return nfields, nflux, nsource, names
+
+
+# --------------------------------------------------------------------------
+# Dedimensionalize: SI values -> nondimensional values -> lattice values
+# --------------------------------------------------------------------------
+def value_scale(d: Dim, characteristics):
+    """The characteristic value of dimension d built from characteristic
+    quantities [(Dim, SI value), ...] that span the base dimensions (e.g. a
+    length, a sound speed, a density and a gas constant): with B the matrix
+    of their exponent columns, d = B c and the scale is prod_j value_j^c_j."""
+    cols = [c[0].e for c in characteristics]
+    B = sp.Matrix([[sp.Rational(Fraction(c[i]).numerator, Fraction(c[i]).denominator) for c in cols]
+                   for i in range(len(BASE))])
+    if B.shape[0] != B.shape[1] or B.det() == 0:
+        raise ValueError("the characteristic quantities must form a basis of the base dimensions")
+    v = sp.Matrix([sp.Rational(Fraction(x).numerator, Fraction(x).denominator) for x in d.e])
+    c = B.inv() * v
+    out = 1.0
+    for (dim, val), ex in zip(characteristics, c):
+        out *= float(val) ** float(ex)
+    return out
+
+
+def nondimensional(scheme: Scheme, si_values: dict, characteristics):
+    """Parameter values of the scheme in units of the characteristic scales
+    (the value non-dimensionalization of the supplement's SI listing):
+    X* = X_SI / value_scale(D(X))."""
+    return {n: si_values[n] / value_scale(scheme.dims[n], characteristics) for n in si_values}
+
+
+def lattice_values(scheme: Scheme, values: dict, dx: float, dt: float):
+    """Alg. 1, Dedimensionalize: a quantity X with scaling (p, q) becomes
+    X dx^-p dt^-q on the lattice (dx = dt = 1 there).  values: name ->
+    value in the units the grid spacings dx, dt are measured in."""
+    out = {}
+    for n, v in values.items():
+        p, q = scheme.pq[n]
+        out[n] = float(v) * float(dx) ** (-float(p)) * float(dt) ** (-float(q))
+    return out
+
+
+def field_factors(scheme: Scheme, dx: float, dt: float):
+    """Per-field factors dx^-p dt^-q taking the fields (conserved and
+    trackers) to lattice units."""
+    return [float(dx) ** (-float(scheme.pq[n][0])) * float(dt) ** (-float(scheme.pq[n][1])) for n in scheme.names]
 
 
 def lattice_factors(p, q, dx, dt):
@@ -416,7 +548,7 @@ def fluctuation_form(scheme: Scheme):
     component), the deviation is (N(Q0 + dQ) M(Q0) - N(Q0) M(Q0 + dQ)) /
     (M(Q0 + dQ) M(Q0)); the expanded numerator keeps only terms with a dQ
     factor, so no large reference-sized terms cancel in floating point (the
-    Automated Reference and Equilibrium Shifting of Sec. 2.6, done by the
+    Automated Reference and Equilibrium Shifting of Sec. 2.5.2, done by the
     compiler).  Tracker references are zero.  Returns (q0, dq, [[delta]])."""
     K = scheme.K
     q0 = [sp.Symbol(f"q0_{k}", real=True) for k in range(K)]

@@ -95,6 +95,33 @@ def nsf3d17():
     return m.compile()
 
 
+@functools.lru_cache(maxsize=None)
+def nsf3d_strain():
+    """The same 3D NSF with the velocity and T = p / rho tracked, compiled with
+    Alg. 1's strain reduction: the stress depends on the velocity gradient
+    only through its symmetric part, so its 9 trackers become the 6 strain
+    trackers (00, 11, 22, 01, 02, 12), and the state is the 14-field basis
+    of the paper's homogenized NSF at porosity 1."""
+    m = Model("nsf3d_strain", 3)
+    rho = m.state("rho", DENSITY)
+    mom = m.state("m", DENSITY * VELOCITY, rank=1)
+    E = m.state("E", PRESSURE)
+    gamma = m.param("gamma", ONE)
+    mu = m.param("mu", DYNAMIC_VISCOSITY)
+    kappa = m.param("kappa", DYNAMIC_VISCOSITY)
+    uex = mom / rho
+    pex = (gamma - 1) * (E - dot(mom, uex) / 2)
+    u = m.tracked("u", uex, VELOCITY)
+    T = m.tracked("T", pex / rho, PRESSURE / DENSITY)
+    gu = grad(u)
+    tau = mu * (gu + gu.T - 2 * trace(gu) / 3 * eye(3))
+    m.tracker_velocity(u)
+    m.law(dt(rho) + div(mom))
+    m.law(dt(mom) + div(outer(mom, u) + pex * eye(3) - tau))
+    m.law(dt(E) + div((E + pex) * u - tau * u - kappa * grad(T)))
+    return m.compile(strain="u")
+
+
 # Systems emitted into the library: (library name, declaration, parameter
 # defaults, default reference state).  The references are the backgrounds of
 # the paper's manufactured solutions in units rho0 = cs = 1, as for the

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def test_buckingham_pi_scalings():
-    """Sec. 2.6: with mass eliminated through the density and temperature
+    """Sec. 2.5.1: with mass eliminated through the density and temperature
     through the gas constant, a velocity scales as (1, -1), the density as
     (0, 0), and the dynamic viscosity and the thermal conductivity both as a
     length^2 / time diffusivity (2, -1)."""
@@ -117,3 +117,75 @@ def test_fluctuation_form_is_the_flux_difference(decl):
         a = np.array(f(Q0, dQ, par, 3.0))
         b = fF(Q0 + dQ, par, 3.0) - fF(Q0, par, 3.0)
         assert np.abs(a - b).max() < 1e-13 * max(1.0, np.abs(b).max())
+
+
+def test_strain_reduced_nsf_equals_the_homogenized_oracle_at_porosity_one():
+    """Alg. 1's optional strain reduction: the 3D NSF declared with the
+    velocity tracked compiles, with the symmetric velocity-gradient tensor
+    reduced to 6 strain trackers, to the 14-field basis of the paper's
+    homogenized NSF; its fluxes and sources equal the oracle's hand-written
+    homogenized-NSF system at porosity 1 (pure fluid) at random states."""
+    s = declared.nsf3d_strain()
+    assert s.names == ["rho", "m0", "m1", "m2", "E", "S_u_00", "S_u_11", "S_u_22", "S_u_01", "S_u_02", "S_u_12",
+                       "G_T_0", "G_T_1", "G_T_2"]
+    assert s.pq["S_u_01"] == (0, -1) and s.pq["G_T_0"] == (1, -2)      # velocity / length; (2, -2) / length
+    par = {"gamma": 1.4, "mu": 0.013, "kappa": 0.05}
+    o = oracle.Oracle("hcnsf3d_trk14", "D3Q7", (4, 4, 4), 0.001, 0.01, 0.6, 3.0, dict(par, eta=0.1),
+                      Q0=[1.0] + [0.0] * 13)
+    itg = 1.0 / o.params["tau_grad"]
+    fF, fS = s.numpy_flux_source()
+    pv = [par[n] for n in s.param_names]
+    rng = np.random.default_rng(13)
+    for _ in range(25):
+        q = rng.uniform(-1, 1, 14)
+        q[0] = rng.uniform(0.8, 1.2)
+        q[4] = rng.uniform(4, 6)
+        Fo, So = o.flux(q), o.source(q)
+        Fg, Sg = fF(q, pv, itg), fS(q, pv, itg)
+        assert np.abs(Fg - Fo).max() < 1e-12 * max(1.0, np.abs(Fo).max())
+        assert np.abs(Sg - So).max() < 1e-12 * max(1.0, np.abs(So).max())
+
+
+def test_strain_reduction_refuses_an_antisymmetric_dependence():
+    """A flux that reads the rotation part of grad u cannot be carried by
+    strain trackers."""
+    m = C.Model("rot", 2)
+    rho = m.state("rho", C.DENSITY)
+    mom = m.state("m", C.DENSITY * C.VELOCITY, rank=1)
+    u = m.tracked("u", mom / rho, C.VELOCITY)
+    gu = C.grad(u)
+    m.tracker_velocity(u)
+    m.law(C.dt(rho) + C.div(mom))
+    m.law(C.dt(mom) + C.div(C.outer(mom, u) + (gu - gu.T)))
+    with pytest.raises(ValueError, match="antisymmetric"):
+        m.compile(strain="u")
+
+
+# the supplement's SI listing of the 2D compressible NSF: characteristic
+# references density and gas constant, working scales rho0 = 1.225 kg/m^3 and
+# c_s = 340 m/s on a unit length; SI parameter values of its manufactured case
+SI_CNSF = {"gamma": 1.4, "mu": 3.52, "kappa": 4980.0, "R_gas": 287.0}
+CHAR_CNSF = [(C.LENGTH, 1.0), (C.VELOCITY, 340.0), (C.DENSITY, 1.225), (C.GAS_CONSTANT, 287.0)]
+
+
+def test_si_declaration_dedimensionalizes_to_the_nondimensional_parameters():
+    """Value non-dimensionalization divides each SI value by the scale its
+    dimension takes from the characteristic quantities: mu / (rho0 c_s L),
+    kappa / (R rho0 c_s L) (temperature through the gas constant), R -> 1,
+    gamma unchanged; Alg. 1 then scales to the lattice by dx^-p dt^-q."""
+    s = declared.cnsf2d()
+    nd = C.nondimensional(s, SI_CNSF, CHAR_CNSF)
+    want = {"gamma": 1.4, "mu": 3.52 / (1.225 * 340.0), "kappa": 4980.0 / (287.0 * 1.225 * 340.0), "R_gas": 1.0}
+    for n, v in want.items():
+        assert nd[n] == pytest.approx(v, rel=1e-12), n
+    dx, dt = 1.0 / 48, 2.0 / 48 ** 2
+    lv = C.lattice_values(s, nd, dx, dt)
+    assert lv["mu"] == pytest.approx(nd["mu"] * dt / dx ** 2, rel=1e-14)        # (p, q) = (2, -1)
+    assert lv["kappa"] == pytest.approx(nd["kappa"] * dt / dx ** 2, rel=1e-14)
+    assert lv["R_gas"] == nd["R_gas"]             # a characteristic reference is lattice-invariant, (0, 0)
+    assert lv["gamma"] == 1.4
+    ff = C.field_factors(s, dx, dt)
+    assert ff[s.names.index("rho")] == 1.0
+    assert ff[s.names.index("m0")] == pytest.approx(dt / dx, rel=1e-14)
+    assert ff[s.names.index("E")] == pytest.approx((dt / dx) ** 2, rel=1e-14)
+    assert ff[s.names.index("G_E_1")] == pytest.approx(dt ** 2 / dx, rel=1e-14)
