@@ -2,15 +2,18 @@
 """Throughput of the fused collide-and-stream step on one MI355X.
 
 Workload (one "step" = one fused collide-and-stream launch over the whole
-grid: load, moments, flux, equilibrium, sources, BGK, streamed store):
-shallow water (h, hu, hv), D2Q9 populations per field, 1024 x 1024
-periodic, FP32 shifted populations, synthetic seeded initial depth (8 random
-Fourier modes of amplitude 0.05, |k| <= 8, fluid at rest), g = 1,
-dt = 0.2 dx, tau = 1/2 + 2 dt.  Inputs are resident in HBM before the timed
-region.
+grid: load, moments, flux, equilibrium, sources including the in-kernel
+manufactured-solution forcing, BGK, streamed store): the 3D compressible
+Navier-Stokes-Fourier cascade with 5 conserved fields (rho, rho u, E) and
+12 gradient trackers (velocity gradient, temperature gradient), D3Q7
+populations per field, 256^3 periodic, FP32 shifted populations, smooth
+manufactured solution at Mach 0.1, Re 100, Pr 0.71, dt = 0.05 dx,
+tau = 1/2 + 20 dt, tracker relaxation g_tau = 3.  The population pair is
+16 GB, far beyond the 256 MB Infinity Cache, so the step is HBM-bound.
+Inputs are resident in HBM before the timed region.
 
 Printed: one JSON line with MLUPS x variables (the metric), the HBM
-roofline of the step kernel (algorithmic 2*K*Q*4 = 216 bytes per cell
+roofline of the step kernel (algorithmic 2*K*Q*4 = 952 bytes per cell
 update over the kernel's average launch duration: HIP events on the stream
 the kernel runs on bracket the K back-to-back launches), the FP64 CPU oracle on a
 bounded sample of the same workload, and the adjoint/forward time ratio of
@@ -26,11 +29,11 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E nameplate
-KERNEL_SOURCES = ["paper_2607_05668_amd/csrc/step_kernels.hpp", "paper_2607_05668_amd/csrc/sys_swe.hip",
+KERNEL_SOURCES = ["paper_2607_05668_amd/csrc/step_kernels.hpp", "paper_2607_05668_amd/csrc/sys_nsf17.hip",
                   "paper_2607_05668_amd/csrc/kernels.hip", "paper_2607_05668_amd/csrc/systems.hpp",
                   "paper_2607_05668_amd/csrc/lattices.hpp", "paper_2607_05668_amd/csrc/impl.hpp",
                   "paper_2607_05668_amd/csrc/dual.hpp", "paper_2607_05668_amd/csrc/device_common.hpp"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_swe1024.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_nsf256.json")
 
 
 def kernel_source_hash():
@@ -78,24 +81,36 @@ def time_steps(torch, g, k, per_launch):
 
 
 def cpu_baseline(target_s=10.0):
+    """The FP64 C oracle on a bounded sample of the benchmark workload: the
+    same 17-field D3Q7 system, recipe and manufactured forcing (evaluated
+    with numpy from the SymPy residual at t + dt/2 each step) on a 64^3
+    grid, for about target_s seconds of steps."""
     import numpy as np
     import oracle
+    from oracle import mms
     from paper_2607_05668_amd import inputs
-    p = inputs.PRESETS["swe1024"]
-    o = oracle.make(p, Q0=[1.0, 0.0, 0.0])
-    o.init(inputs.swe_initial(p.n))
+    p = inputs.PRESETS["nsf256"]
+    m = inputs.NsfMms()
+    n = 64
+    o = oracle.make(p, n=n, Q0=m.reference())
+    _, fS = mms.nsf17(m.gamma, m.rho0, m.p0, m.u0, m.amp, m.mu, m.kappa, o.params["tau_grad"])
+    X, Y, Z = inputs.grid3(n)
+    o.init(inputs.nsf_exact(n, 0.0, m))
+    src = lambda t: fS(X, Y, Z, t)   # noqa: E731
     t = time.perf_counter()
-    o.step(1)
+    o.step(1, source=src)
     one = time.perf_counter() - t
-    n = max(1, min(5000, int(target_s / max(one, 1e-3))))
+    k = max(1, min(2000, int(target_s / max(one, 1e-3))))
     t = time.perf_counter()
-    o.step(n)
+    o.step(k, source=src)
     dt = time.perf_counter() - t
-    cells = p.n * p.n
+    cells = n ** 3
     assert np.isfinite(o.moments()).all()
-    return {"value": round(cells * n * 3 / dt / 1e6, 3), "unit": "MLUPS x variables", "cores": oracle.num_threads(),
+    return {"value": round(cells * k * 17 / dt / 1e6, 3), "unit": "MLUPS x variables", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"FP64 C oracle, same 1024x1024 D2Q9 shallow-water workload, {n} steps ({dt:.1f} s)"}
+            "sample": f"FP64 C oracle (OpenMP over cells) on the same 17-field D3Q7 NSF cascade with its "
+                      f"manufactured forcing at 64^3 instead of 256^3 (per-cell work does not depend on the grid), "
+                      f"{k} steps ({dt:.1f} s), forcing evaluated with numpy each step"}
 
 
 def adjoint_ratio(torch):
@@ -181,6 +196,9 @@ def extra_runs(torch, lbm, inputs):
         del g
 
     p = inputs.PRESETS["swe1024"]
+    # the shallow-water configuration's own grid: its 226 MB population pair
+    # fits the 256 MB Infinity Cache, so this line is cache-resident, not HBM
+    one("swe2d_D2Q9_f32_1024_cache_resident", p, 1024, "f32", 1000, 216, inputs.swe_initial(1024))
     one("swe2d_D2Q9_f32_2048", p, 2048, "f32", 200, 216, inputs.swe_initial(2048))
     # two-relaxation-time collision (magic parameter 3/16) on the same workload
     one("swe2d_D2Q9_f32_2048_trt", p, 2048, "f32", 200, 216, inputs.swe_initial(2048),
@@ -216,8 +234,6 @@ def extra_runs(torch, lbm, inputs):
         coef=inputs.hcnsf_coefficients(256, 0.0))
     p = inputs.PRESETS["advdiff64"]
     one("advdiff_D2Q5_f64_64", p, 64, "f64", 200, 240, inputs.advdiff_initial(64))
-    p = inputs.PRESETS["nsf256"]
-    one("nsf3d_trk17_D3Q7_f32_256_mms", p, 256, "f32", 50, 952, inputs.nsf_exact(256, 0.0))
     return out
 
 
@@ -274,6 +290,43 @@ def roofline_table(torch, lbm, inputs, steps):
             "steps": steps, "rows": rows}
 
 
+def counters_run(torch, lbm, inputs, workload, warmup):
+    """For rocprofv3 --pmc: warm-up and ten launches of one workload's step
+    (or adjoint) kernel, then five copies of exactly 1 GiB with the
+    library's copy kernel, whose counter readings scale the step kernel's."""
+    launches = warmup + 10
+    if workload == "adjoint512":
+        from paper_2607_05668_amd import rollout
+        run = rollout.SweRollout(n=512, steps=launches, ckpt=launches)
+        h0 = torch.tensor(inputs.swe_height(512), device="cuda")
+        b = torch.tensor(inputs.topography_gradient(512), device="cuda", dtype=torch.float32)
+        hN = run.forward(h0, b)
+        run.backward(hN / hN.numel())
+        del run
+    else:
+        if workload == "nsf256":
+            p = inputs.PRESETS["nsf256"]
+            g = lbm.from_preset(p)
+            g.init(inputs.nsf_exact(p.n, 0.0))
+        elif workload == "swe2048":
+            g = lbm.from_preset(inputs.PRESETS["swe1024"], n=2048)
+            g.init(inputs.swe_initial(2048))
+        else:
+            g = lbm.from_preset(inputs.PRESETS["neohooke2048"], storage=workload.split("_")[1])
+            g.init(inputs.neohooke_initial(2048))
+        g.step(launches)
+        del g
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    n = 1 << 30
+    a = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty(n, dtype=torch.uint8, device="cuda")
+    for _ in range(5):
+        lbm.bw_copy(b, a, n)
+    torch.cuda.synchronize()
+    print(json.dumps({"counters_run": workload, "launches": launches, "copy_bytes": n, "copies": 5}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -281,7 +334,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the adjoint ratio, probe and extra workloads")
-    ap.add_argument("--counters", action="store_true", help="short run for rocprofv3 counter collection")
+    ap.add_argument("--counters", nargs="?", const="nsf256", default=None,
+                    choices=["nsf256", "swe2048", "neohooke_f16", "neohooke_f16ne", "adjoint512"],
+                    help="short run of one workload for rocprofv3 counter collection (default: the benchmark's)")
     ap.add_argument("--table", action="store_true",
                     help="instead of the benchmark: every system in FP32 and FP64 on the paper's lattices")
     args = ap.parse_args()
@@ -296,22 +351,13 @@ def main():
     if args.table:
         print(json.dumps(roofline_table(torch, lbm, inputs, min(args.steps, 50))))
         return
-    p = inputs.PRESETS["swe1024"]
-    g = lbm.from_preset(p)
-    g.init(inputs.swe_initial(p.n))
-    g.step(args.warmup)
     if args.counters:
-        # counter runs (rocprofv3 --pmc): a short stepping burst, then copies of
-        # a known size whose counter readings scale the stepping kernel's
-        g.step(50)
-        n = 1 << 30
-        a = torch.zeros(n, dtype=torch.uint8, device="cuda")
-        b = torch.empty(n, dtype=torch.uint8, device="cuda")
-        for _ in range(5):
-            lbm.bw_copy(b, a, n)
-        torch.cuda.synchronize()
-        print(json.dumps({"counters_run": True, "step_launches": 50 + args.warmup, "copy_bytes": n, "copies": 5}))
+        counters_run(torch, lbm, inputs, args.counters, args.warmup)
         return
+    p = inputs.PRESETS["nsf256"]
+    g = lbm.from_preset(p)
+    g.init(inputs.nsf_exact(p.n, 0.0))
+    g.step(args.warmup)
     # the timed region: K back-to-back launches on the stepper's stream
     # bracketed by HIP events on that stream; the average launch duration is
     # the region's time over K
@@ -340,18 +386,21 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "shallow water (h, hu, hv), D2Q9 per field, 1024x1024 periodic, FP32 shifted "
-                               "populations, seeded 8-mode depth field, one fused collide-and-stream launch per step",
-                   "cells": cells, "fields": K, "lattice": "D2Q9", "storage": "f32",
+        "config": {"workload": "3D compressible Navier-Stokes-Fourier cascade, 5 conserved + 9 velocity-gradient "
+                               "+ 3 temperature-gradient trackers, D3Q7 per field, 256^3 periodic, FP32 shifted "
+                               "populations, manufactured solution (Mach 0.1, Re 100, Pr 0.71) forced in-kernel, "
+                               "one fused collide-and-stream launch per step",
+                   "cells": cells, "fields": K, "lattice": "D3Q7", "storage": "f32",
                    "bytes_per_cell_update": 2 * K * g.Q * 4},
         "mlups": round(cells * args.steps / total_ms / 1e3, 1),
         "hbm_roofline_pct": round(100.0 * achieved / HBM_PEAK_GBPS, 2),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                     "kernel": "k_step<SysSWE, D2Q9, float>", "kernel_ms": round(kern_ms, 5),
+                     "kernel": "k_step<SysNSF17, D3Q7, float>", "kernel_ms": round(kern_ms, 5),
                      "algorithmic_bytes_per_launch": bytes_per_launch},
     }
     del g
+    torch.cuda.empty_cache()
     if not args.no_extra:
         line.update(adjoint_ratio(torch))
         line["probe_peak_GBps"] = probe_peak(torch, lbm)
@@ -359,7 +408,7 @@ def main():
         # without arithmetic, at the benchmark grid and at 2048^2 (HBM-resident)
         pat = {"swe1024": probe_pattern(torch, lbm, 1024), "swe2048": probe_pattern(torch, lbm, 2048)}
         line["probe_pattern_GBps"] = pat
-        line["roofline"]["frac_of_pattern_probe"] = round(achieved / pat["swe1024"], 4)
+        line["roofline"]["frac_of_copy_probe"] = round(achieved / line["probe_peak_GBps"], 4)
         line["extra"] = extra_runs(torch, lbm, inputs)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()

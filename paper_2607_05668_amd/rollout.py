@@ -36,9 +36,11 @@ class SweRollout:
         self.tmp = s.new_adjoint()
         self.Q_init = None
         self.b = None
+        self.generation = 0          # forwards run so far; backward must follow its own forward
 
     def forward(self, h0, b):
         torch, s = self.torch, self.stepper
+        self.generation += 1
         h0 = h0.to(device=s.device, dtype=torch.float64)
         self.b = b.to(device=s.device, dtype=s.real).contiguous()
         s.set_field("grad_zb", self.b)
@@ -77,10 +79,20 @@ def _function():
             ctx.runner = runner
             ctx.b_dtype = b.dtype
             ctx.h_dtype = h0.dtype
-            return runner.forward(h0, b)
+            out = runner.forward(h0, b)
+            # the runner keeps one set of snapshots: remember which forward
+            # they belong to, and let torch's version counters catch in-place
+            # edits of h0 or b between forward and backward
+            ctx.generation = runner.generation
+            ctx.save_for_backward(h0, b)
+            return out
 
         @staticmethod
         def backward(ctx, grad_hN):
+            ctx.saved_tensors                     # raises if h0 or b changed in place
+            if ctx.runner.generation != ctx.generation:
+                raise RuntimeError("SweRollout ran another forward since this graph was built: its snapshots "
+                                   "belong to that later forward; use one runner per pending backward")
             dh0, db = ctx.runner.backward(grad_hN)
             return dh0.to(ctx.h_dtype), db.to(ctx.b_dtype), None
 
