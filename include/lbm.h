@@ -272,6 +272,20 @@ int lbm_moments(lbm_state *h, void *Q_out_dev, int absolute, int out_dtype);
  * required for RELL2 / RELLINF.  Synchronises the bound stream. */
 int lbm_reduce(lbm_state *h, int what, const double *ref_dev, double *host_out);
 
+/* lbm_reduce without the bound workspace, for callers that cannot allocate
+ * device memory (and so cannot size an aux buffer of their own): the same
+ * reductions, same kernels and same results, with the partial sums kept in
+ * a static device array of 295,488 bytes per GPU (2 x 18 x 1024 + 72
+ * doubles: the largest system's partials and final slots).  The array is
+ * part of the loaded library and lives until the process ends; its address
+ * is looked up once per device, with that device current, on the first
+ * call.  Arguments, results and errors as for lbm_reduce; LBM_EINVAL if the
+ * reduction needed more than the static array (no system does).  Every call
+ * on one GPU shares that GPU's array: calls that overlap on one GPU (from
+ * several threads or handles at once) race and must be serialised by the
+ * caller.  Allocates nothing; synchronises the bound stream. */
+int lbm_reduce_static(lbm_state *h, int what, const double *ref_dev, double *host_out);
+
 /* Current step count and time. */
 long long lbm_step_count(const lbm_state *h);
 double lbm_time(const lbm_state *h);

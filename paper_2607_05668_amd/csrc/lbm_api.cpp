@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -853,6 +854,62 @@ static int reduce_with(lbm_state *h, int what, const double *ref_dev, double *ho
 int lbm_reduce(lbm_state *h, int what, const double *ref_dev, double *host_out)
 {
     return reduce_with(h, what, ref_dev, host_out, h ? (double *)h->aux : nullptr);
+}
+
+// Reduction workspace of lbm_reduce_static: one array per GPU, in device
+// memory the code object reserves when it is loaded, so the entry point
+// allocates nothing.  Host code reaches it only through the address
+// hipGetSymbolAddress returns on each device (the array's name is a host
+// stand-in, not a device address).
+constexpr size_t kStaticScratchDoubles = (size_t)2 * LBM_MAXK * kRedBlocks + 4 * LBM_MAXK;
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// address of this device's scratch array, looked up once per device with
+// that device current
+double *static_scratch(lbm_state *h, int *rc)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        *rc = hipfail(h, e, "reduce_static: hipGetDevice");
+        return nullptr;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        *rc = fail(h, LBM_EINVAL, "reduce_static: device index beyond the library's table");
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            *rc = hipfail(h, e != hipSuccess ? e : hipErrorInvalidSymbol, "reduce_static: hipGetSymbolAddress");
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+int lbm_reduce_static(lbm_state *h, int what, const double *ref_dev, double *host_out)
+{
+    int rc = check_ready(h);
+    if (rc) return rc;
+    // the passes need 2 K partial slots per first-pass workgroup and the
+    // final slots after the partials of the largest system
+    const size_t need = (size_t)2 * h->K * kRedBlocks;
+    if (h->K > LBM_MAXK || need + 2 * LBM_MAXK > kStaticScratchDoubles)
+        return fail(h, LBM_EINVAL, "reduce_static: the reduction needs more than the static workspace of " +
+                                       std::to_string(kStaticScratchDoubles * sizeof(double)) + " bytes");
+    double *ws = static_scratch(h, &rc);
+    if (!ws) return rc;
+    return reduce_with(h, what, ref_dev, host_out, ws);
 }
 
 long long lbm_step_count(const lbm_state *h) { return h ? h->nsteps : 0; }

@@ -23,7 +23,7 @@ STORAGE = {"f64": F64, "f32": F32, "f16": F16, "f16ne": F16NE}
 
 EXPORTS = ["lbm_create", "lbm_last_error", "lbm_num_fields", "lbm_num_velocities", "lbm_set_param", "lbm_get_param",
            "lbm_set_storage", "lbm_set_reference", "lbm_get_reference", "lbm_required_bytes", "lbm_bind",
-           "lbm_set_field", "lbm_init_moments", "lbm_step", "lbm_step_record", "lbm_moments", "lbm_reduce",
+           "lbm_set_field", "lbm_init_moments", "lbm_step", "lbm_step_record", "lbm_moments", "lbm_reduce", "lbm_reduce_static",
            "lbm_step_count", "lbm_time", "lbm_adjoint_seed", "lbm_adjoint_step", "lbm_adjoint_to_initial",
            "lbm_save", "lbm_load", "lbm_snapshot", "lbm_restore", "lbm_bw_copy", "lbm_bw_streams",
            "lbm_destroy"]
@@ -68,6 +68,7 @@ def load_library():
     lib.lbm_step_record.argtypes = [vp, c_int, vp]
     lib.lbm_moments.argtypes = [vp, vp, c_int, c_int]
     lib.lbm_reduce.argtypes = [vp, c_int, vp, dp]
+    lib.lbm_reduce_static.argtypes = [vp, c_int, vp, dp]
     lib.lbm_step_count.restype = ctypes.c_longlong
     lib.lbm_step_count.argtypes = [vp]
     lib.lbm_time.restype = c_double
@@ -228,14 +229,16 @@ class Stepper:
         self._check(self.lib.lbm_moments(self.h, out.data_ptr(), 1 if absolute else 0, code))
         return out
 
-    def reduce(self, what, ref=None):
-        """FP64 reduction (lbm_reduce)."""
+    def reduce(self, what, ref=None, static=False):
+        """FP64 reduction (lbm_reduce; with static=True lbm_reduce_static,
+        which uses the library's static workspace instead of the bound one)."""
         out = np.zeros(2 * 18)
         rp = None
         if ref is not None:
             ref = self._field_tensor(ref, self.torch.float64, self.K)
             rp = ref.data_ptr()
-        self._check(self.lib.lbm_reduce(self.h, what, rp, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        fn = self.lib.lbm_reduce_static if static else self.lib.lbm_reduce
+        self._check(fn(self.h, what, rp, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         n = {RED_SUMS: self.K, RED_RELL2: self.K, RED_RELLINF: self.K, RED_MAXSPEED: 2, RED_NONFINITE: 1}[what]
         return out[:n].copy()
 

@@ -194,9 +194,9 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
         lbm.load_library()
 
 
-def test_check_every_host_checks():
+def test_check_every_and_static_reduce_host_checks():
     """Failure-detection interval: a non-negative whole step count, readable
-    back."""
+    back; the static-workspace reduction refuses an unbound handle."""
     lib = lbm.load_library()
     h = ctypes.c_void_p(lib.lbm_create(b"swe2d", b"D2Q9", 64, 64, 1, 0.6, 1e-3, 1e-2))
     assert lib.lbm_set_param(h, b"check_every", -1.0) == lbm.LBM_EINVAL
@@ -204,4 +204,6 @@ def test_check_every_host_checks():
     assert lib.lbm_set_param(h, b"check_every", 5.0) == 0
     v = ctypes.c_double()
     assert lib.lbm_get_param(h, b"check_every", ctypes.byref(v)) == 0 and v.value == 5.0
+    out = (ctypes.c_double * 36)()
+    assert lib.lbm_reduce_static(h, lbm.RED_SUMS, None, out) == lbm.LBM_ENOTBOUND
     lib.lbm_destroy(h)
