@@ -190,6 +190,21 @@ __global__ __launch_bounds__((step_block<Sys, St>())) void k_step(const St *__re
     }
     const I own = tile_offset<K, Q>(yx) * S;
     const size_t slab = (size_t)K * Q * (size_t)((P + kTile - 1) / kTile * kTile);   // elements per z-slab
+    // The manufactured forcing of the 3D NSF system depends on the cell's
+    // coordinates and the time only: it is evaluated before the populations
+    // are loaded, so that its temporaries are not live beside them.
+    R Smms[5] = {R(0), R(0), R(0), R(0), R(0)};
+    if constexpr (Sys::id == SYS_NSF17) {
+        if (p.mms.on) {
+            // the manufactured fields are periodic on the unit cube: the
+            // coordinates enter reduced to [0, 1), so the sine arguments stay
+            // below 2 pi on any grid (on the unit grid nothing changes)
+            auto unit = [](R v) { return v - floor(v); };
+            nsf_mms_source<R>(p.mms, p.phys, unit((R)x * p.mms.dx), unit((R)y * p.mms.dx), unit((R)z * p.mms.dx),
+                              Smms);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
 
     R f[K][Q];
 #pragma unroll
@@ -266,17 +281,8 @@ __global__ __launch_bounds__((step_block<Sys, St>())) void k_step(const St *__re
         for (int k = 0; k < K; ++k) Sk[k] += *byte_at(p.sext + k * (size_t)p.C, cell * (I)sizeof(R));
     }
     if constexpr (Sys::id == SYS_NSF17) {
-        if (p.mms.on) {
-            // the manufactured fields are periodic on the unit cube: the
-            // coordinates enter reduced to [0, 1), so the sine arguments stay
-            // below 2 pi on any grid (on the unit grid nothing changes)
-            auto unit = [](R v) { return v - floor(v); };
-            R S5[5];
-            nsf_mms_source<R>(p.mms, p.phys, unit((R)x * p.mms.dx), unit((R)y * p.mms.dx), unit((R)z * p.mms.dx),
-                              S5);
 #pragma unroll
-            for (int k = 0; k < 5; ++k) Sk[k] += S5[k];
-        }
+        for (int k = 0; k < 5; ++k) Sk[k] += Smms[k];
     }
     // BGK relaxation post = omega feq + (1 - omega) f written as
     // post = e + c1 (e - f) with c1 = omega - 1 exactly representable (the
