@@ -128,8 +128,11 @@ PRESETS = {
                       "acoustic", 0.2, 2.0, None, {"g": 1.0}),
     "sweadj512": Preset("sweadj512", "swe2d", "D2Q9", 512, "f32", 500,
                         "acoustic", 0.2, 2.0, None, {"g": 1.0}),
+    # binary16 storage: tau_R = 20 (the paper raises tau_R as it lowers the
+    # precision; at its single-precision tau_R = 2, omega = 1.997 and the
+    # rounding of the stored non-equilibrium part decays over ~300 steps)
     "neohooke2048": Preset("neohooke2048", "neohooke2d", "D2Q9", 2048, "f16", 2000,
-                           "acoustic", 0.1, 2.0, None,
+                           "acoustic", 0.1, 20.0, None,
                            {"rho0": 1.0, "mu_s": 1.0, "lambda_s": 2.0}),
     # the paper's suite on the same kernel (single-precision recipes of its
     # configuration table, D2Q5 as in the paper)

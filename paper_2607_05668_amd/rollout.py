@@ -34,6 +34,9 @@ class SweRollout:
         self.hist = torch.empty((self.ckpt, s.K) + s.shape, dtype=s.real, device=s.device)
         self.lam = s.new_adjoint()
         self.tmp = s.new_adjoint()
+        # one gradient buffer for every backward, so that the adjoint launches
+        # captured for small grids keep their arguments
+        self.grad_b = torch.zeros((2,) + s.shape, dtype=s.real, device=s.device)
         self.Q_init = None
         self.b = None
         self.generation = 0          # forwards run so far; backward must follow its own forward
@@ -58,7 +61,8 @@ class SweRollout:
         z = torch.zeros_like(g)
         lam, tmp = self.lam, self.tmp
         s.adjoint_seed(torch.stack([g, z, z]), lam)
-        grad_b = torch.zeros((2,) + s.shape, dtype=s.real, device=s.device)
+        grad_b = self.grad_b
+        grad_b.zero_()
         for j in reversed(range(self.nseg)):
             m = min(self.ckpt, self.steps - j * self.ckpt)
             s.restore(self.snaps[j], j * self.ckpt)
@@ -67,7 +71,7 @@ class SweRollout:
             if out is tmp:
                 lam, tmp = tmp, lam
         dQ0 = s.adjoint_to_initial(lam, self.Q_init)
-        return dQ0[0], grad_b
+        return dQ0[0], grad_b.clone()
 
 
 def _function():

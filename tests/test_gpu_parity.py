@@ -153,15 +153,11 @@ def test_advdiff_fp64_matches_oracle():
     assert rel(Qg[0] - 1.0, ex[0] - 1.0) == pytest.approx(rel(Qo[0] - 1.0, ex[0] - 1.0), rel=1e-9)
 
 
-F16_V_XFAIL = pytest.mark.xfail(
-    reason="FP16 storage of the shifted populations (the paper's form): velocity rel L2 1.9e-3 against "
-           "its own norm after 2000 steps, above 1e-3; the deformation gradient is at 1.3e-4", strict=False)
-
-
-@pytest.mark.parametrize("storage,tol", [("f32", 1e-6), pytest.param("f16", 1e-3, marks=F16_V_XFAIL),
-                                         ("f16ne", 1e-3)])
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-6), ("f16", 1e-3), ("f16ne", 1e-3)])
 def test_neohooke_matches_oracle(storage, tol):
-    """C5 at its parity grid 256^2 for the full 2000 steps."""
+    """C5 at its parity grid 256^2 for the full 2000 steps, with the
+    binary16 recipe (f = 0.1, tau_R = 20): the paper's shifted FP16 storage
+    within 1e-3 (measured F 4.9e-5, v 7.2e-4)."""
     print(f"neohooke2d D2Q9 {storage} 256x256 2000 steps", flush=True)
     p = inputs.PRESETS["neohooke2048"]
     g = lbm.from_preset(p, n=256, storage=storage)
@@ -172,8 +168,24 @@ def test_neohooke_matches_oracle(storage, tol):
     o = twin(g, p.params, parity.recipe(256, p.scaling, p.f, p.tau_r), Q0=[1.0, 0.0, 0.0, 1.0, 0.0, 0.0])
     o.init(Q)
     o.step(2000)
-    Qo = o.moments()
-    parity.check_fields({"F": slice(0, 4), "v": slice(4, 6)}, Qg, Qo, tol)
+    parity.check_fields({"F": slice(0, 4), "v": slice(4, 6)}, Qg, o.moments(), tol)
+
+
+@pytest.mark.xfail(reason="FP16 storage of the shifted populations at the single-precision rate tau_R = 2 "
+                          "(omega = 1.997): velocity rel L2 1.97e-3 against its own norm after 2000 steps, above "
+                          "1e-3 (tau_R 5: 1.37e-3, 10: 9.8e-4, 20: 7.2e-4)", strict=True)
+def test_neohooke_fp16_at_the_single_precision_rate():
+    print("neohooke2d D2Q9 f16 256x256 2000 steps, tau_R = 2", flush=True)
+    p = inputs.PRESETS["neohooke2048"]
+    g = lbm.from_preset(p, n=256, storage="f16", tau_r=2.0)
+    Q = inputs.neohooke_initial(256)
+    g.init(Q)
+    g.step(2000)
+    Qg = g.moments().cpu().numpy()
+    o = twin(g, p.params, parity.recipe(256, p.scaling, p.f, 2.0), Q0=[1.0, 0.0, 0.0, 1.0, 0.0, 0.0])
+    o.init(Q)
+    o.step(2000)
+    parity.check_fields({"F": slice(0, 4), "v": slice(4, 6)}, Qg, o.moments(), 1e-3)
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16", "f16ne"])
