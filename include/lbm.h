@@ -215,9 +215,9 @@ int lbm_get_reference(const lbm_state *h, double *Q0_out);
 
 /* Bytes the caller must provide: which = 0 one population buffer
  * (K*Q*nz*ceil(nx ny / 64)*64*sizeof(storage), the tile-blocked layout; for
- * LBM_F16NE the binary16 deviations [K][Q][cells] padded to 256 bytes
- * followed by K*cells floats of moments); which = 1 scratch for
- * reductions. */
+ * LBM_F16NE the binary16 deviations in the same tile-blocked layout,
+ * padded to 256 bytes, followed by K*cells floats of moments); which = 1
+ * scratch for reductions. */
 size_t lbm_required_bytes(const lbm_state *h, int which);
 
 /* Bind caller-owned device memory: two population buffers (A/B, each

@@ -17,8 +17,10 @@
 // computation as the sender's).  Per cell update this moves K Q 2 bytes of
 // populations and K 4 bytes of moments each way.
 //
-// Buffer layout (each of A and B): populations [K][Q][cells] binary16, padded
-// to 256 bytes, then moments [K][cells] float.
+// Buffer layout (each of A and B): the binary16 deviations in the
+// tile-blocked layout of the step kernels ([tiles][K][Q][kTile], the cells
+// padded to whole tiles), padded to 256 bytes, then moments [K][cells]
+// float.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -26,7 +28,17 @@
 
 #include "device_common.hpp"
 
-inline size_t ne_pop_bytes(long long C, int K, int Q) { return (((size_t)K * Q * C * 2) + 255) & ~(size_t)255; }
+inline size_t ne_pop_bytes(long long C, int K, int Q)
+{
+    return (((size_t)K * Q * (size_t)padded_plane(C) * 2) + 255) & ~(size_t)255;
+}
+
+// element offset of deviation (k, i) of cell c (2D: c = y nx + x)
+template <int K, int Q>
+__device__ inline size_t ne_at(int k, int i, long long c)
+{
+    return (size_t)tile_offset<K, Q>(c) + (size_t)(k * Q + i) * kTile;
+}
 
 // Rebuild the pre-collision populations of cell (x, y, z) from the senders'
 // deviations and stored moments.
@@ -58,7 +70,7 @@ __device__ inline void ne_load(const _Float16 *__restrict__ g, const float *__re
         }
 #pragma unroll
         for (int k = 0; k < K; ++k)
-            f[k][i] = (float)g[(size_t)(k * Q + i) * C + src[i]] * p.inv_scale[k] + ei[k];
+            f[k][i] = (float)g[ne_at<K, Q>(k, i, src[i])] * p.inv_scale[k] + ei[k];
     }
 }
 
@@ -76,12 +88,13 @@ __device__ inline int pmod(int v, int n)
     return r < 0 ? r + n : r;
 }
 
-template <class Sys, class Lat, bool NT>
+template <class Sys, class Lat, bool NT, bool O32>
 __global__ __launch_bounds__(kNeTX * kNeTY) void k_step_ne(const _Float16 *__restrict__ gin,
                                                            const float *__restrict__ Min,
                                                            _Float16 *__restrict__ gout, float *__restrict__ Mout,
                                                            const KParams<float> p)
 {
+    using I = typename Index<O32>::T;
     constexpr int K = Sys::K, Q = Lat::Q, D = Lat::D;
     constexpr int HX = kNeTX + 2, HY = kNeTY + 2, NH = HX * HY, NTH = kNeTX * kNeTY;
     __shared__ float sM[K][NH];
@@ -90,6 +103,20 @@ __global__ __launch_bounds__(kNeTX * kNeTY) void k_step_ne(const _Float16 *__res
     const int tilesx = (p.nx + kNeTX - 1) / kNeTX;
     const unsigned t = (unsigned)xcd_tile(blockIdx.x, gridDim.x);
     const int tx0 = (int)(t % (unsigned)tilesx) * kNeTX, ty0 = (int)(t / (unsigned)tilesx) * kNeTY;
+    const int lx = (int)threadIdx.x % kNeTX, ly = (int)threadIdx.x / kNeTX;
+    const int x = tx0 + lx, y = ty0 + ly;
+    const bool live = x < p.nx && y < p.ny;
+    // This cell's pulled binary16 deviations do not depend on the halo work
+    // below: their loads are issued first and are in flight meanwhile.
+    _Float16 gr[K][Q];
+    if (live) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const I src = tile_offset<K, Q>((I)wrapi(y - Lat::cy[i], p.ny) * (I)p.nx + (I)wrapi(x - Lat::cx[i], p.nx));
+#pragma unroll
+            for (int k = 0; k < K; ++k) gr[k][i] = *byte_at(gin + (size_t)(k * Q + i) * kTile, src * (I)2);
+        }
+    }
     for (int h = threadIdx.x; h < NH; h += NTH) {
         const int hy = h / HX, hx = h - hy * HX;
         const size_t c = (size_t)pmod(ty0 + hy - 1, p.ny) * p.nx + pmod(tx0 + hx - 1, p.nx);
@@ -105,14 +132,12 @@ __global__ __launch_bounds__(kNeTX * kNeTY) void k_step_ne(const _Float16 *__res
         }
     }
     __syncthreads();
-    const int lx = (int)threadIdx.x % kNeTX, ly = (int)threadIdx.x / kNeTX;
-    const int x = tx0 + lx, y = ty0 + ly;
-    if (x >= p.nx || y >= p.ny) return;                 // no barrier follows
+    if (!live) return;                                  // no barrier follows
     const long long cell = (long long)y * p.nx + x;
+    const I own = tile_offset<K, Q>((I)cell) * (I)2;
     float f[K][Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const size_t src = (size_t)wrapi(y - Lat::cy[i], p.ny) * p.nx + wrapi(x - Lat::cx[i], p.nx);
         const int h = (ly + 1 - Lat::cy[i]) * HX + (lx + 1 - Lat::cx[i]);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -126,7 +151,7 @@ __global__ __launch_bounds__(kNeTX * kNeTY) void k_step_ne(const _Float16 *__res
                 ExactEq<Lat>::feq(sM[k][h], 0.0f, G, e);
                 ei = e[i];
             }
-            f[k][i] = (float)gin[(size_t)(k * Q + i) * C + src] * p.inv_scale[k] + ei;
+            f[k][i] = (float)gr[k][i] * p.inv_scale[k] + ei;
         }
     }
     float dQ[K];
@@ -160,11 +185,11 @@ __global__ __launch_bounds__(kNeTX * kNeTY) void k_step_ne(const _Float16 *__res
         for (int i = 1; i < Q; ++i) {
             const float d = e[i] - f[k][i];
             const _Float16 hv = (_Float16)(fmaf(p.c1[k], d, s[i]) * p.scale[k]);
-            st_pop<NT>(gout + (size_t)(k * Q + i) * C + cell, hv);
+            st_pop<NT>(byte_at(gout + (size_t)(k * Q + i) * kTile, own), hv);
             acc += (f[k][i] - e[i]) - (float)hv * p.inv_scale[k];
         }
         const float g0 = (f[k][0] - e0) + acc;
-        st_pop<NT>(gout + (size_t)(k * Q) * C + cell, (_Float16)(g0 * p.scale[k]));
+        st_pop<NT>(byte_at(gout + (size_t)(k * Q) * kTile, own), (_Float16)(g0 * p.scale[k]));
         st_pop<NT>(Mout + (size_t)k * C + cell, dQ[k]);
     }
 }
@@ -212,7 +237,7 @@ __device__ inline void ne_init_cell(const double *__restrict__ Qin, const KParam
             }
             const double gv = feq - (double)ei;
             if constexpr (STORE)
-                g[(size_t)(k * Q + i) * C + cell] = (_Float16)(gv * (double)pf.scale[k]);
+                g[ne_at<K, Q>(k, i, cell)] = (_Float16)(gv * (double)pf.scale[k]);
             else
                 mx[k] = fabs(gv) > mx[k] ? fabs(gv) : mx[k];
         }
@@ -285,9 +310,12 @@ __global__ __launch_bounds__(kBlock) void k_reduce1_ne(const _Float16 *__restric
     const unsigned nb = gridDim.x;
     if (what == 4) {
         double cnt = 0.0;
-        const size_t n = (size_t)K * Q * C;
-        for (size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (size_t)nb * kBlock)
+        // deviations in the tile-blocked layout; the padding of the last tile is never read
+        const size_t n = (size_t)K * Q * (size_t)padded_plane((long long)C);
+        for (size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (size_t)nb * kBlock) {
+            if ((j / ((size_t)K * Q * kTile)) * kTile + j % kTile >= C) continue;
             cnt += isfinite((float)g[j]) ? 0.0 : 1.0;
+        }
         for (size_t j = (size_t)blockIdx.x * kBlock + threadIdx.x; j < (size_t)K * C; j += (size_t)nb * kBlock)
             cnt += isfinite(M[j]) ? 0.0 : 1.0;
         const double r = block_reduce_sum(cnt, sh);
@@ -371,17 +399,23 @@ struct ImplNE {
         return (const float *)((const char *)buf + ne_pop_bytes(h.C, Sys::K, Lat::Q));
     }
 
+    template <bool NT, bool O32>
+    static void launch(const lbm_state_impl &h, const void *fin, void *fout, const KParams<float> &p, hipStream_t s)
+    {
+        hipLaunchKernelGGL((k_step_ne<Sys, Lat, NT, O32>), dim3(step_grid(h)), dim3(kNeTX * kNeTY), 0, s, gp(h, fin),
+                           mp(h, fin), (_Float16 *)fout, (float *)mp(h, fout), p);
+    }
     static hipError_t step(const lbm_state_impl &h, const void *fin, void *fout, void *qhist, hipStream_t s)
     {
         if (qhist) return hipErrorInvalidValue;
         const KParams<float> p = h.kparams<float>(h.t0 + (h.nsteps + 0.5) * h.dt);
         const bool nt = 2 * (ne_pop_bytes(h.C, Sys::K, Lat::Q) + (size_t)Sys::K * h.C * 4) > kLastLevelCacheBytes;
+        // 32-bit byte offsets when the deviations stay below 4 GiB
+        const bool o32 = ne_pop_bytes(h.C, Sys::K, Lat::Q) <= 0xffffffffull;
         if (nt)
-            hipLaunchKernelGGL((k_step_ne<Sys, Lat, true>), dim3(step_grid(h)), dim3(kNeTX * kNeTY), 0, s, gp(h, fin),
-                               mp(h, fin), (_Float16 *)fout, (float *)mp(h, fout), p);
+            o32 ? launch<true, true>(h, fin, fout, p, s) : launch<true, false>(h, fin, fout, p, s);
         else
-            hipLaunchKernelGGL((k_step_ne<Sys, Lat, false>), dim3(step_grid(h)), dim3(kNeTX * kNeTY), 0, s, gp(h, fin),
-                               mp(h, fin), (_Float16 *)fout, (float *)mp(h, fout), p);
+            o32 ? launch<false, true>(h, fin, fout, p, s) : launch<false, false>(h, fin, fout, p, s);
         return hipGetLastError();
     }
     static hipError_t init(const lbm_state_impl &h, const double *Q, void *fout, hipStream_t s)

@@ -596,8 +596,9 @@ size_t lbm_required_bytes(const lbm_state *h, int which)
 {
     if (!h) return 0;
     if (which == 0) {
-        if (h->storage == LBM_F16NE)   // binary16 deviations, padded, then FP32 moments
-            return ((((size_t)h->K * h->Q * (size_t)h->C * 2) + 255) & ~(size_t)255) + (size_t)h->K * h->C * 4;
+        if (h->storage == LBM_F16NE)   // binary16 deviations (tile-blocked, padded), then FP32 moments
+            return ((((size_t)h->K * h->Q * (size_t)padded_plane(h->C) * 2) + 255) & ~(size_t)255) +
+                   (size_t)h->K * h->C * 4;
         // tile-blocked [nz][tiles][K][Q][kTile], each slab padded to whole tiles
         const size_t s = h->storage == LBM_F64 ? 8 : (h->storage == LBM_F32 ? 4 : 2);
         return (size_t)h->K * h->Q * (size_t)padded_plane((long long)h->nx * h->ny) * (size_t)h->nz * s;
@@ -674,20 +675,21 @@ int lbm_bind(lbm_state *h, void *pop_a, void *pop_b, void *aux, void *hip_stream
 int lbm_set_field(lbm_state *h, const char *name, const void *dev_ptr)
 {
     if (!h || !name) return LBM_EINVAL;
-    h->epoch += 1;
-    if (h->sys == SYS_SWE && !std::strcmp(name, "grad_zb")) {
-        h->field_b = dev_ptr;
+    // kernels read a field through its pointer: captured launches stay valid
+    // while the pointer does (the contents may change between steps)
+    auto attach = [h](const void *&slot, const void *ptr) {
+        if (slot != ptr) h->epoch += 1;
+        slot = ptr;
         return LBM_OK;
-    }
+    };
+    if (h->sys == SYS_SWE && !std::strcmp(name, "grad_zb")) return attach(h->field_b, dev_ptr);
     if (!std::strcmp(name, "source")) {
         if (h->storage == LBM_F16NE) return fail(h, LBM_EINVAL, "no explicit source field with F16NE storage");
-        h->field_src = dev_ptr;
-        return LBM_OK;
+        return attach(h->field_src, dev_ptr);
     }
     if (h->sys == SYS_HCNSF && !std::strcmp(name, "coef")) {
         if (h->storage == LBM_F16NE) return fail(h, LBM_EINVAL, "no coefficient field with F16NE storage");
-        h->field_b = dev_ptr;
-        return LBM_OK;
+        return attach(h->field_b, dev_ptr);
     }
     return fail(h, LBM_EINVAL, std::string("unknown field '") + name + "' for this system");
 }

@@ -53,7 +53,9 @@ def forced_pair(n, steps):
     fS = mms.compiled(fS)
     X, Y, Z = inputs.grid3(n)
     o.init(Q)
-    o.step(steps, source=lambda t: fS(X, Y, Z, t))
+    while o.nsteps < steps:                  # progress of the long oracle runs
+        o.step(min(50, steps - o.nsteps), source=lambda t: fS(X, Y, Z, t))
+        print(f"  oracle {n}^3: {o.nsteps}/{steps} steps", flush=True)
     return Qg, o.moments(), g, o
 
 
