@@ -43,7 +43,7 @@ struct MmsParams {
     int on;
     R amp, rho0, p0, u0, cbar2;      // shape parameters of the exact fields
     R t;                              // evaluation time t_n + dt/2
-    R k;                              // wavenumber 2 pi
+    R k;                              // wavenumber 2 pi (phases evaluated as sinpi(2 X))
     R dx;
 };
 

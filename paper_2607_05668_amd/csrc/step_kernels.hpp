@@ -40,7 +40,18 @@ __device__ inline void nsf_mms_source(const MmsParams<R> &m, const Phys<R> &p, R
 {
     using J = Dual<R, 4>;
     const R k = m.k, A = m.amp, t = m.t;
-    const R sx = sin(k * X), cx = cos(k * X), sy = sin(k * Y), cy = cos(k * Y), sz = sin(k * Z), cz = cos(k * Z);
+    // sin(k X) and cos(k X) for k = 2 pi and X in [0, 1): 2 X is exact and
+    // sinpi / cospi reduce it exactly, where the product k X would carry a
+    // rounding of up to half an ulp of 2 pi into every phase
+    auto sinp = [](R v) {
+        if constexpr (std::is_same<R, float>::value) return sinpif(R(2) * v);
+        else return sinpi(R(2) * v);
+    };
+    auto cosp = [](R v) {
+        if constexpr (std::is_same<R, float>::value) return cospif(R(2) * v);
+        else return cospi(R(2) * v);
+    };
+    const R sx = sinp(X), cx = cosp(X), sy = sinp(Y), cy = cosp(Y), sz = sinp(Z), cz = cosp(Z);
     const R st = sin(t), ct = cos(t);
     // products of per-axis sines and cosines with all first derivatives
     // and the second spatial derivatives needed for the trackers

@@ -1,0 +1,116 @@
+"""Writes storage_floor.json: the binary32 storage floor of a workload -- the
+relative L2 and L-infinity distance, per field group, between the FP64
+oracle and the same oracle whose populations are rounded to binary32 after
+the initialisation and after every step.  No single-precision stepper that
+stores its populations in binary32 can be expected to sit closer to the FP64
+oracle than this, element by element: where the flow amplifies rounding
+(a steepening front), the floor's L-infinity distance shows by how much.
+
+Cases (argument, default all):
+  c2       shallow water, D2Q9, 1024^2 periodic, acoustic recipe f = 0.2,
+           tau_R = 2, g = 1, 1000 steps, reference (1, 0, 0), initial
+           fields inputs.swe_initial(1024)
+  c3_64,   3D compressible NSF with 9 + 3 trackers, D3Q7, 64^3 / 128^3,
+  c3_128   the configuration's recipe (acoustic f = 0.05, tau_R = 20,
+           g_tau = 3), 500 steps of the manufactured solution with its
+           forcing (SymPy residual, generated C), reference = background
+
+Calls only the oracle, its forcing and the seeded input generators; c2
+takes about five minutes on eight cores, c3_128 about half an hour.  Run
+from the repository root:
+
+    python tests/golden/make_storage_floor.py [c2 c3_64 c3_128]
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from oracle import mms  # noqa: E402
+from paper_2607_05668_amd import inputs  # noqa: E402
+
+OUT = os.path.join(HERE, "storage_floor.json")
+
+
+def _rel_l2(a, b):
+    return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
+
+
+def _rel_linf(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def _binary32(f):
+    return f.astype(np.float32).astype(np.float64)
+
+
+def floor_run(make, Q, steps, groups, report_every=100, source=None):
+    """(exact, rounded) oracle pair over `steps` (source(t): explicit source
+    at t, or None); returns {group: {l2, linf}}."""
+    a, b = make(), make()
+    a.init(Q)
+    b.init(Q)
+    b.f = _binary32(b.f)
+    t0 = time.time()
+    while a.nsteps < steps:
+        S = None if source is None else source(a.t + 0.5 * a.dt)
+        a.step(1, source=None if S is None else (lambda t: S))
+        b.step(1, source=None if S is None else (lambda t: S))
+        b.f = _binary32(b.f)
+        if a.nsteps % report_every == 0:
+            print(f"  step {a.nsteps}/{steps} ({time.time() - t0:.0f} s)", flush=True)
+    Qa, Qb = a.moments(), b.moments()
+    return {name: {"l2": _rel_l2(Qb[s], Qa[s]), "linf": _rel_linf(Qb[s], Qa[s])} for name, s in groups.items()}
+
+
+def case_c2():
+    n, steps, f, tau_r = 1024, 1000, 0.2, 2.0
+    dx, dt, tau = oracle.recipe(n, "acoustic", f, tau_r)
+
+    def make():
+        return oracle.Oracle("swe2d", "D2Q9", (n, n), dt, dx, tau, None, {"g": 1.0}, Q0=[1.0, 0.0, 0.0])
+    res = floor_run(make, inputs.swe_initial(n), steps, {"h": slice(0, 1), "hu": slice(1, 3)})
+    return {"system": "swe2d", "lattice": "D2Q9", "n": n, "steps": steps, "f": f, "tau_r": tau_r, "groups": res}
+
+
+def case_c3(n):
+    steps, f, tau_r, g_tau = 500, 0.05, 20.0, 3.0
+    dx, dt, tau = oracle.recipe(n, "acoustic", f, tau_r)
+    m = inputs.NsfMms()
+    par = {k: v for k, v in inputs.nsf_params(m).items() if k in ("gamma", "mu", "kappa")}
+
+    def make():
+        return oracle.Oracle("nsf3d_trk17", "D3Q7", (n, n, n), dt, dx, tau, g_tau, par, Q0=m.reference(),
+                             omega_tracker=1.0 / (g_tau + 1.0))
+    _, fS = mms.nsf17(m.gamma, m.rho0, m.p0, m.u0, m.amp, m.mu, m.kappa, g_tau * dt)
+    fS = mms.compiled(fS)
+    X, Y, Z = inputs.grid3(n)
+    groups = {"rho": slice(0, 1), "m": slice(1, 4), "E": slice(4, 5), "G_u": slice(5, 14), "G_T": slice(14, 17)}
+    res = floor_run(make, inputs.nsf_exact(n, 0.0, m), steps, groups, 50, source=lambda t: fS(X, Y, Z, t))
+    return {"system": "nsf3d_trk17", "lattice": "D3Q7", "n": n, "steps": steps, "f": f, "tau_r": tau_r,
+            "g_tau": g_tau, "groups": res}
+
+
+CASES = {"c2": case_c2, "c3_64": lambda: case_c3(64), "c3_128": lambda: case_c3(128)}
+
+
+def main(names):
+    out = json.load(open(OUT)) if os.path.exists(OUT) else {}
+    out["_source"] = "written by tests/golden/make_storage_floor.py from the FP64 oracle (no library values)"
+    for name in names:
+        print(f"{name}:", flush=True)
+        out[name] = CASES[name]()
+        print(json.dumps(out[name]["groups"]), flush=True)
+    with open(OUT, "w") as fh:
+        json.dump(out, fh, indent=1)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:] or sorted(CASES))

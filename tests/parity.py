@@ -16,7 +16,12 @@
   rounding errors of single-precision storage behave like a smooth random
   field, whose maximum over 10^4 - 10^7 cells sits about 4-5 standard
   deviations out, while the maximum of the reference field is one to three
-  times its RMS.
+  times its RMS.  Where the flow itself amplifies rounding (a steepening
+  front), the binary32 storage floor -- the FP64 oracle against itself with
+  its populations rounded to binary32 every step, written by
+  ``tests/golden/make_storage_floor.py`` -- can exceed that bar in a few
+  cells; a test then passes ``floor`` and the group's L-infinity bar becomes
+  ``FLOOR_FACTOR`` times the floor's, if that is larger.
 """
 from __future__ import annotations
 
@@ -27,6 +32,7 @@ import numpy as np
 F32_STEP = 2.0 ** -24          # unit roundoff of binary32 (round to nearest)
 F64_STEP = 2.0 ** -52
 LINF_FACTOR = 5.0
+FLOOR_FACTOR = 2.0
 
 
 def rel_l2(a, b):
@@ -39,17 +45,27 @@ def rel_linf(a, b):
     return float(np.max(np.abs(a - b))) / float(np.max(np.abs(b)))
 
 
-def check_fields(groups, Qg, Qo, tol, label=""):
+def linf_bar(tol, floor_linf=None):
+    """L-infinity bar of a group with L2 bar tol and, if given, the
+    storage floor's L-infinity distance."""
+    bar = LINF_FACTOR * tol
+    return bar if floor_linf is None else max(bar, FLOOR_FACTOR * floor_linf)
+
+
+def check_fields(groups, Qg, Qo, tol, label="", floor=None):
     """Per field group (name -> index or slice into axis 0): relative L2 <=
-    tol and relative L-infinity <= LINF_FACTOR tol.  Returns {name: (l2, linf)}."""
+    tol and relative L-infinity <= linf_bar(tol, floor[name]["linf"]) (floor:
+    a storage-floor record of the group, or None).  Returns {name: (l2, linf)}."""
     out = {}
     for name, s in groups.items():
         e2, ei = rel_l2(Qg[s], Qo[s]), rel_linf(Qg[s], Qo[s])
         out[name] = (e2, ei)
-        print(f"{label}{name}: rel L2 {e2:.3e}  rel Linf {ei:.3e}", flush=True)
+        fl = "" if not floor else f"  (storage floor: L2 {floor[name]['l2']:.3e}, Linf {floor[name]['linf']:.3e})"
+        print(f"{label}{name}: rel L2 {e2:.3e}  rel Linf {ei:.3e}{fl}", flush=True)
     for name, (e2, ei) in out.items():
+        bar = linf_bar(tol, floor[name]["linf"] if floor else None)
         assert e2 <= tol, f"{label}{name}: rel L2 {e2:.3e} > {tol:.1e}"
-        assert ei <= LINF_FACTOR * tol, f"{label}{name}: rel Linf {ei:.3e} > {LINF_FACTOR * tol:.1e}"
+        assert ei <= bar, f"{label}{name}: rel Linf {ei:.3e} > {bar:.1e}"
     return out
 
 
