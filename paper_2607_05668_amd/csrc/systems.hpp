@@ -762,7 +762,8 @@ struct SysNeoHooke {
 // every product ab - a0 b0 written as da b + a0 db.
 struct SysNSF17 {
     static constexpr int K = 17, D = 3, id = 3;
-    static constexpr bool precise = false;   // plain exact-moment equilibrium (VALU budget)
+    static constexpr bool precise = false;   // no dual-number flux correction (register budget)
+    static constexpr bool ffeq = true;       // float-float equilibria from the plain-float flux
     static constexpr bool compensated = true;   // two-sum moments dQ = hi + lo
     static constexpr bool tracker(int k) { return k >= 5; }
 
@@ -858,7 +859,8 @@ struct SysNSF17 {
 // dissipative terms is the terms themselves.
 struct SysHCNSF {
     static constexpr int K = 14, D = 3, id = 12;
-    static constexpr bool precise = false;
+    static constexpr bool precise = false;   // no dual-number flux correction (register budget)
+    static constexpr bool ffeq = true;       // float-float equilibria from the plain-float flux
     static constexpr bool compensated = true;
     static constexpr bool tracker(int k) { return k >= 5; }
     // coefficient field: 4 values per cell, read by the flux as well
