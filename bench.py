@@ -234,6 +234,19 @@ def extra_runs(torch, lbm, inputs):
         coef=inputs.hcnsf_coefficients(256, 0.0))
     p = inputs.PRESETS["advdiff64"]
     one("advdiff_D2Q5_f64_64", p, 64, "f64", 200, 240, inputs.advdiff_initial(64))
+    # one GPU's share of the 3D NSF workload split over eight GPUs along z:
+    # a 256 x 256 x 32 slab at the 256^3 spacing (periodic here; a sharded
+    # run would exchange the z faces instead)
+    p = inputs.PRESETS["nsf256"]
+    dx, dt, tau = lbm.recipe(256, p.scaling, p.f, p.tau_r)
+    g = lbm.Stepper(p.system, p.lattice, (32, 256, 256), tau, dt, dx, "f32", dict(p.params, g_tau=p.g_tau))
+    g.init(inputs.nsf_exact(256, 0.0)[:, :32])
+    g.step(100)
+    total, kern = time_steps(torch, g, 100, per_launch=False)
+    out["nsf3d_trk17_D3Q7_f32_256x256x32_share"] = {
+        "mlups": round(g.C / kern / 1e3, 1), "mlups_x_vars": round(g.C * g.K / kern / 1e3, 1),
+        "ms_per_step": round(kern, 5), "algorithmic_GBps": round(952 * g.C / kern / 1e6, 1)}
+    del g
     return out
 
 
