@@ -90,11 +90,11 @@ def test_hcnsf_with_porosity_matches_oracle(storage, n, tol, coef):
 def test_hcnsf_fp16_storage():
     """Binary16 shifted populations (per-field power-of-two scales, FP32
     arithmetic) on the porous MMS state: the conserved fields hold 1e-3
-    (measured rho 2.3e-5, rho u 1.6e-4, E 3.8e-5 at 60 steps); the tracker
-    populations carry the velocity deviation times lam / (cs2 tau_grad)
-    around a much smaller gradient, so binary16 rounding of them leaves
-    G_u at 3.1e-3 and G_T at 1.1e-3, above the FP16 tolerance (expected
-    failure, as for the plain FP16 storage of the elasticity workload)."""
+    (measured rho 2.3e-5, rho u 1.6e-4, E 3.8e-5 at 60 steps); the
+    trackers follow the gradient of the velocity the binary16 momentum
+    carries, which amplifies its rounding by |u| / |du| and 1 / (k dx):
+    G_u 3.1e-3 and G_T 1.1e-3, above the FP16 tolerance (expected failure;
+    a slower tracker relaxation, larger g_tau, measured worse)."""
     print("hcnsf3d_trk14 D3Q7 f16 24^3 60 steps, coefficient field", flush=True)
     n = 24
     g, o, Bo = make_pair((n, n, n), "f16", inputs.hcnsf_exact(n, 0.4), inputs.hcnsf_coefficients(n, 0.4), 20.0)
