@@ -160,6 +160,27 @@ def probe_peak(torch, lbm):
     return round(2 * n / ms / 1e6, 1)
 
 
+def probe_pattern3(torch, lbm, n, fields=17, reps=10):
+    """The 3D step's memory-access pattern without arithmetic at n^3 (7
+    fields float planes pulled and stored, the step's launch shape): GB/s
+    of 2 x 28 fields n^3 bytes."""
+    nbytes = 28 * fields * n ** 3
+    a = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    for _ in range(3):
+        lbm.bw_streams3(b, a, n, n, n, fields)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        lbm.bw_streams3(b, a, n, n, n, fields)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return round(2 * nbytes / ms / 1e6, 1)
+
+
 def probe_pattern(torch, lbm, n, fields=3, reps=20):
     """The D2Q9 step's memory-access pattern without arithmetic at n x n
     (9 fields float planes pulled and stored): GB/s of 2 x 36 fields n^2 bytes."""
@@ -417,11 +438,15 @@ def main():
     if not args.no_extra:
         line.update(adjoint_ratio(torch))
         line["probe_peak_GBps"] = probe_peak(torch, lbm)
-        # the step's own access pattern (27 pulled + 27 stored float planes)
-        # without arithmetic, at the benchmark grid and at 2048^2 (HBM-resident)
-        pat = {"swe1024": probe_pattern(torch, lbm, 1024), "swe2048": probe_pattern(torch, lbm, 2048)}
+        # the steps' own access patterns without arithmetic: the benchmark's
+        # (119 pulled + 119 stored float planes on D3Q7 at 256^3), and the
+        # shallow-water step's (27 + 27 on D2Q9, at 1024^2 cache-resident and
+        # at 2048^2)
+        pat = {"nsf256": probe_pattern3(torch, lbm, 256), "swe1024": probe_pattern(torch, lbm, 1024),
+               "swe2048": probe_pattern(torch, lbm, 2048)}
         line["probe_pattern_GBps"] = pat
         line["roofline"]["frac_of_copy_probe"] = round(achieved / line["probe_peak_GBps"], 4)
+        line["roofline"]["frac_of_pattern_probe"] = round(achieved / pat["nsf256"], 4)
         line["extra"] = extra_runs(torch, lbm, inputs)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()

@@ -346,6 +346,18 @@ int lbm_restore(lbm_state *h, const void *dev_buf, long long step);
 int lbm_bw_copy(void *dst, const void *src, size_t n, void *hip_stream);
 int lbm_bw_streams(void *dst, const void *src, int nx, int ny, int fields, void *hip_stream);
 
+/* lbm_bw_streams3 is the same probe for the 3D D3Q7 step: src and dst each
+ * hold 7 * fields float planes of nx * ny * nz cells in the step's
+ * tile-blocked layout ([nz][tiles][7 fields][64], each z-slab padded to
+ * whole tiles: byte size 28 fields ceil(nx ny / 64) 64 nz); cell (x, y, z)
+ * reads plane j at the periodic pull position (x, y, z) - c_(j mod 7) (D3Q7
+ * order of the population layout) and writes it, non-temporally, to plane
+ * j at (x, y, z).  It is launched in the 17-field step's shape: 512-thread
+ * workgroups, one per CU.  fields must be 14 or 17; LBM_EINVAL otherwise,
+ * for null pointers, nx, ny, nz < 1 or a slab beyond 4 GiB.  Asynchronous
+ * on hip_stream. */
+int lbm_bw_streams3(void *dst, const void *src, int nx, int ny, int nz, int fields, void *hip_stream);
+
 /* Release the handle (does not touch bound buffers). */
 void lbm_destroy(lbm_state *h);
 

@@ -115,6 +115,7 @@ double lbm_gen_reference(int gen, int k);
 const Launchers *lbm_launchers_ne(int sys, int lat);   // storage LBM_F16NE
 hipError_t lbm_launch_copy(void *dst, const void *src, size_t n, hipStream_t s);
 hipError_t lbm_launch_streams(void *dst, const void *src, int nx, int ny, int fields, hipStream_t s);
+hipError_t lbm_launch_streams3(void *dst, const void *src, int nx, int ny, int nz, int fields, hipStream_t s);
 
 // Host-side state behind the opaque lbm_state handle.
 struct lbm_state_impl {

@@ -76,6 +76,60 @@ hipError_t lbm_launch_streams(void *dst, const void *src, int nx, int ny, int fi
     return hipGetLastError();
 }
 
+// The 3D D3Q7 step's memory pattern without arithmetic, in the step's
+// population layout ([nz][tiles][7 F][kTile], each z-slab padded to whole
+// tiles): plane j of cell (x, y, z) pulled from (x, y, z) - c_(j mod 7),
+// periodic, stored at (x, y, z) with non-temporal stores.  Launched like the
+// 17-field step: 512-thread workgroups over z-slab tiles in the XCD order,
+// one workgroup per CU (an LDS reservation of kStreams3Lds bytes), which
+// is the occupancy the step's registers allow.
+constexpr int kStreams3Block = 512;
+constexpr int kStreams3Lds = 96 * 1024;
+template <int N>
+__global__ __launch_bounds__(kStreams3Block) void k_streams3(const float *__restrict__ src, float *__restrict__ dst,
+                                                           int nx, int ny, int nz)
+{
+    extern __shared__ float reserve[];
+    const unsigned P = (unsigned)nx * (unsigned)ny;
+    const unsigned tpp = (P + kStreams3Block - 1) / kStreams3Block;
+    const unsigned t = (unsigned)xcd_tile(blockIdx.x, gridDim.x);
+    const int z = (int)(t / tpp);
+    const unsigned yx = (t - (unsigned)z * tpp) * kStreams3Block + threadIdx.x;
+    if (yx >= P) return;
+    const int y = (int)(yx / (unsigned)nx), x = (int)(yx - (unsigned)y * nx);
+    const size_t slab = (size_t)N * (size_t)padded_plane((long long)P);
+    float v[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const int i = j % 7;
+        const unsigned s = (unsigned)wrapi(y - D3Q7::cy[i], ny) * nx + (unsigned)wrapi(x - D3Q7::cx[i], nx);
+        const int zs = wrapi(z - D3Q7::cz[i], nz);
+        v[j] = *byte_at(src + (size_t)zs * slab + (size_t)j * kTile, tile_offset<N, 1>(s) * 4u);
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+        st_pop<true>(byte_at(dst + (size_t)z * slab + (size_t)j * kTile, tile_offset<N, 1>(yx) * 4u), v[j]);
+    if (threadIdx.x == 0x7fffffffu) reserve[0] = v[0];      // keeps the reservation; never taken
+}
+
+hipError_t lbm_launch_streams3(void *dst, const void *src, int nx, int ny, int nz, int fields, hipStream_t s)
+{
+    const size_t P = (size_t)nx * ny;
+    if (padded_plane((long long)P) * 28 * fields > 0xffffffffull) return hipErrorInvalidValue;   // 32-bit slab offsets
+    const unsigned tpp = (unsigned)((P + kStreams3Block - 1) / kStreams3Block);
+    const dim3 grid(tpp * (unsigned)nz);
+    auto go = [&](auto kern) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, kStreams3Lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, grid, dim3(kStreams3Block), kStreams3Lds, s, (const float *)src, (float *)dst, nx, ny,
+                           nz);
+        return hipGetLastError();
+    };
+    if (fields == 14) return go(k_streams3<98>);
+    if (fields == 17) return go(k_streams3<119>);
+    return hipErrorInvalidValue;
+}
+
 // ------------------------------------------------------- host: params ----
 template <class R>
 KParams<R> lbm_state_impl::kparams(double t_half) const

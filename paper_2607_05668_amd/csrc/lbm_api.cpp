@@ -1079,6 +1079,14 @@ int lbm_bw_streams(void *dst, const void *src, int nx, int ny, int fields, void 
     return lbm_launch_streams(dst, src, nx, ny, fields, (hipStream_t)hip_stream) == hipSuccess ? LBM_OK : LBM_EHIP;
 }
 
+int lbm_bw_streams3(void *dst, const void *src, int nx, int ny, int nz, int fields, void *hip_stream)
+{
+    if (!dst || !src || nx < 1 || ny < 1 || nz < 1 || (fields != 14 && fields != 17)) return LBM_EINVAL;
+    const hipError_t e = lbm_launch_streams3(dst, src, nx, ny, nz, fields, (hipStream_t)hip_stream);
+    if (e == hipErrorInvalidValue) return LBM_EINVAL;
+    return e == hipSuccess ? LBM_OK : LBM_EHIP;
+}
+
 void lbm_destroy(lbm_state *h)
 {
     if (h && h->graphs) delete (GraphCache *)h->graphs;

@@ -25,7 +25,7 @@ EXPORTS = ["lbm_create", "lbm_last_error", "lbm_num_fields", "lbm_num_velocities
            "lbm_set_storage", "lbm_set_reference", "lbm_get_reference", "lbm_required_bytes", "lbm_bind",
            "lbm_set_field", "lbm_init_moments", "lbm_step", "lbm_step_record", "lbm_moments", "lbm_reduce", "lbm_reduce_static",
            "lbm_step_count", "lbm_time", "lbm_adjoint_seed", "lbm_adjoint_step", "lbm_adjoint_to_initial",
-           "lbm_save", "lbm_load", "lbm_snapshot", "lbm_restore", "lbm_bw_copy", "lbm_bw_streams",
+           "lbm_save", "lbm_load", "lbm_snapshot", "lbm_restore", "lbm_bw_copy", "lbm_bw_streams", "lbm_bw_streams3",
            "lbm_destroy"]
 
 
@@ -82,6 +82,7 @@ def load_library():
     lib.lbm_restore.argtypes = [vp, vp, ctypes.c_longlong]
     lib.lbm_bw_copy.argtypes = [vp, vp, c_size, vp]
     lib.lbm_bw_streams.argtypes = [vp, vp, c_int, c_int, c_int, vp]
+    lib.lbm_bw_streams3.argtypes = [vp, vp, c_int, c_int, c_int, c_int, vp]
     lib.lbm_destroy.restype = None
     lib.lbm_destroy.argtypes = [vp]
     _lib = lib
@@ -312,6 +313,21 @@ def bw_streams(dst, src, nx, ny, fields, stream=None):
                             ctypes.c_void_p(s.cuda_stream))
     if rc != LBM_OK:
         raise LbmError(rc, "bw_streams failed")
+
+
+def bw_streams3(dst, src, nx, ny, nz, fields, stream=None):
+    """D3Q7 step memory-pattern probe: 7 fields planes of nx*ny*nz floats
+    pulled at the lattice offsets and stored (no arithmetic); see include/lbm.h."""
+    lib = load_library()
+    torch = _torch()
+    need = 28 * fields * ((nx * ny + 63) // 64 * 64) * nz    # tile-blocked z-slabs, padded to 64 cells
+    if dst.numel() * dst.element_size() < need or src.numel() * src.element_size() < need:
+        raise ValueError(f"bw_streams3 needs {need} bytes per buffer")
+    s = stream or torch.cuda.current_stream()
+    rc = lib.lbm_bw_streams3(dst.data_ptr(), src.data_ptr(), int(nx), int(ny), int(nz), int(fields),
+                             ctypes.c_void_p(s.cuda_stream))
+    if rc != LBM_OK:
+        raise LbmError(rc, "bw_streams3 failed")
 
 
 def bw_copy(dst, src, nbytes, stream=None):

@@ -49,6 +49,41 @@ def test_streams_probe_is_the_d2q9_pull(shape, fields):
         assert np.array_equal(d[j], np.roll(planes[j], (CY[i], CX[i]), axis=(0, 1))), j
 
 
+CX3 = [0, 1, -1, 0, 0, 0, 0]
+CY3 = [0, 0, 0, 1, -1, 0, 0]
+CZ3 = [0, 0, 0, 0, 0, 1, -1]
+
+
+def _to_tiles3(planes):
+    """[N, nz, ny, nx] -> the 3D step's layout [nz][tiles][N][64] (each
+    z-slab's cells y nx + x cut into tiles of 64, the last one padded with
+    NaN)."""
+    return np.concatenate([_to_tiles(planes[:, z]) for z in range(planes.shape[1])])
+
+
+def _from_tiles3(buf, N, nz, ny, nx):
+    slab = buf.size // nz
+    return np.stack([_from_tiles(buf[z * slab:(z + 1) * slab], N, ny, nx) for z in range(nz)], axis=1)
+
+
+@pytest.mark.parametrize("shape,fields", [((3, 5, 13), 17), ((4, 16, 32), 14), ((2, 9, 70), 17)])
+def test_streams3_probe_is_the_d3q7_pull(shape, fields):
+    """The 3D pattern probe pulls every plane at the D3Q7 offsets in the
+    step's tile-blocked z-slab layout (ragged last tile of each slab
+    included) and never reads padding."""
+    nz, ny, nx = shape
+    N = 7 * fields
+    planes = np.random.default_rng(5).normal(size=(N, nz, ny, nx)).astype(np.float32)
+    src = torch.tensor(_to_tiles3(planes), device="cuda")
+    dst = torch.full_like(src, float("nan"))
+    lbm.bw_streams3(dst, src, nx, ny, nz, fields)
+    torch.cuda.synchronize()
+    d = _from_tiles3(dst.cpu().numpy(), N, nz, ny, nx)
+    for j in range(N):
+        i = j % 7
+        assert np.array_equal(d[j], np.roll(planes[j], (CZ3[i], CY3[i], CX3[i]), axis=(0, 1, 2))), j
+
+
 def test_copy_probe_copies_with_a_ragged_tail():
     n = (1 << 20) + 7
     src = torch.randint(0, 255, (n,), dtype=torch.uint8, device="cuda")
@@ -64,3 +99,7 @@ def test_probes_reject_bad_arguments():
         lbm.bw_streams(a, a, 64, 64, 3)
     lib = lbm.load_library()
     assert lib.lbm_bw_streams(a.data_ptr(), a.data_ptr(), 1, 1, 4, None) == lbm.LBM_EINVAL
+    assert lib.lbm_bw_streams3(a.data_ptr(), a.data_ptr(), 1, 1, 1, 4, None) == lbm.LBM_EINVAL
+    assert lib.lbm_bw_streams3(a.data_ptr(), a.data_ptr(), 1, 1, 0, 17, None) == lbm.LBM_EINVAL
+    with pytest.raises(ValueError):
+        lbm.bw_streams3(a, a, 64, 64, 2, 17)
