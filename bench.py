@@ -432,6 +432,12 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                      "kernel": "k_step<SysNSF17, D3Q7, float>", "kernel_ms": round(kern_ms, 5),
                      "algorithmic_bytes_per_launch": bytes_per_launch},
+        # the paper's own roofline figure for the nearest system it measures
+        # (its 3D homogenized NSF, 14 fields on D3Q7 in FP32; Performance
+        # section, roofline table), on the hardware it names: context only
+        "paper_roofline_context": {"hardware": "NVIDIA RTX A5000, 680 GB/s measured (BabelStream Triad)",
+                                   "system": "homogenized compressible NSF, 14 fields, D3Q7, FP32",
+                                   "mlups": 546, "bytes_per_cell": 784, "bw_saturation": 0.630},
     }
     del g
     torch.cuda.empty_cache()
