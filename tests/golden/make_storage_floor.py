@@ -14,12 +14,18 @@ Cases (argument, default all):
   c3_128   the configuration's recipe (acoustic f = 0.05, tau_R = 20,
            g_tau = 3), 500 steps of the manufactured solution with its
            forcing (SymPy residual, generated C), reference = background
+  c5_f16_tau20,  neo-Hookean elastodynamics, D2Q9, 256^2, acoustic
+  c5_f16_tau2    f = 0.1, tau_R = 20 (the binary16 recipe) or 2 (the
+           single-precision rate), 2000 steps from inputs.neohooke_initial,
+           reference F = I, v = 0; the populations rounded to binary16 after
+           a per-field power-of-two scale 2^floor(log2(2048 / max |f_k|))
+           chosen on the initial populations (the FP16 storage's rule)
 
 Calls only the oracle, its forcing and the seeded input generators; c2
 takes about five minutes on eight cores, c3_128 about half an hour.  Run
 from the repository root:
 
-    python tests/golden/make_storage_floor.py [c2 c3_64 c3_128]
+    python tests/golden/make_storage_floor.py [c2 c3_64 c3_128 c5_f16_tau20 c5_f16_tau2]
 """
 import json
 import os
@@ -51,19 +57,31 @@ def _binary32(f):
     return f.astype(np.float32).astype(np.float64)
 
 
-def floor_run(make, Q, steps, groups, report_every=100, source=None):
+def _binary16_rounder(f0):
+    """Rounding to scaled binary16 with per-field scales 2^e, e =
+    floor(log2(2048 / max |f_k|)) over the initial populations f0 [K, ...]."""
+    K = f0.shape[0]
+    m = np.abs(f0.reshape(K, -1)).max(axis=1)
+    e = np.where(m > 0, np.floor(np.log2(2048.0 / np.where(m > 0, m, 1.0))), 0.0).clip(-24, 24)
+    s = (2.0 ** e).reshape((K,) + (1,) * (f0.ndim - 1))
+    return lambda f: (f * s).astype(np.float16).astype(np.float64) / s
+
+
+def floor_run(make, Q, steps, groups, report_every=100, source=None, storage="binary32"):
     """(exact, rounded) oracle pair over `steps` (source(t): explicit source
-    at t, or None); returns {group: {l2, linf}}."""
+    at t, or None; storage: binary32, or binary16 with per-field scales);
+    returns {group: {l2, linf}}."""
     a, b = make(), make()
     a.init(Q)
     b.init(Q)
-    b.f = _binary32(b.f)
+    rnd = _binary32 if storage == "binary32" else _binary16_rounder(b.f)
+    b.f = rnd(b.f)
     t0 = time.time()
     while a.nsteps < steps:
         S = None if source is None else source(a.t + 0.5 * a.dt)
         a.step(1, source=None if S is None else (lambda t: S))
         b.step(1, source=None if S is None else (lambda t: S))
-        b.f = _binary32(b.f)
+        b.f = rnd(b.f)
         if a.nsteps % report_every == 0:
             print(f"  step {a.nsteps}/{steps} ({time.time() - t0:.0f} s)", flush=True)
     Qa, Qb = a.moments(), b.moments()
@@ -98,7 +116,22 @@ def case_c3(n):
             "g_tau": g_tau, "groups": res}
 
 
-CASES = {"c2": case_c2, "c3_64": lambda: case_c3(64), "c3_128": lambda: case_c3(128)}
+def case_c5(tau_r):
+    n, steps, f = 256, 2000, 0.1
+    dx, dt, tau = oracle.recipe(n, "acoustic", f, tau_r)
+    par = {"rho0": 1.0, "mu_s": 1.0, "lambda_s": 2.0}
+
+    def make():
+        return oracle.Oracle("neohooke2d", "D2Q9", (n, n), dt, dx, tau, None, par,
+                             Q0=[1.0, 0.0, 0.0, 1.0, 0.0, 0.0])
+    res = floor_run(make, inputs.neohooke_initial(n), steps, {"F": slice(0, 4), "v": slice(4, 6)}, 250,
+                    storage="binary16")
+    return {"system": "neohooke2d", "lattice": "D2Q9", "n": n, "steps": steps, "f": f, "tau_r": tau_r,
+            "storage": "binary16, per-field power-of-two scale", "groups": res}
+
+
+CASES = {"c2": case_c2, "c3_64": lambda: case_c3(64), "c3_128": lambda: case_c3(128),
+         "c5_f16_tau20": lambda: case_c5(20.0), "c5_f16_tau2": lambda: case_c5(2.0)}
 
 
 def main(names):

@@ -166,7 +166,8 @@ def test_advdiff_fp64_matches_oracle():
 def test_neohooke_matches_oracle(storage, tol):
     """C5 at its parity grid 256^2 for the full 2000 steps, with the
     binary16 recipe (f = 0.1, tau_R = 20): the paper's shifted FP16 storage
-    within 1e-3 (measured F 4.9e-5, v 7.2e-4)."""
+    within 1e-3 (measured F 4.9e-5, v 7.2e-4, at the binary16 storage floor
+    of the same run: F 5.4e-5, v 7.9e-4)."""
     print(f"neohooke2d D2Q9 {storage} 256x256 2000 steps", flush=True)
     p = inputs.PRESETS["neohooke2048"]
     g = lbm.from_preset(p, n=256, storage=storage)
@@ -177,12 +178,15 @@ def test_neohooke_matches_oracle(storage, tol):
     o = twin(g, p.params, parity.recipe(256, p.scaling, p.f, p.tau_r), Q0=[1.0, 0.0, 0.0, 1.0, 0.0, 0.0])
     o.init(Q)
     o.step(2000)
-    parity.check_fields({"F": slice(0, 4), "v": slice(4, 6)}, Qg, o.moments(), tol)
+    # binary16 storage: the oracle's own binary16 storage floor is printed beside it
+    floor = FLOOR["c5_f16_tau20"]["groups"] if storage == "f16" else None
+    parity.check_fields({"F": slice(0, 4), "v": slice(4, 6)}, Qg, o.moments(), tol, floor=floor)
 
 
 @pytest.mark.xfail(reason="FP16 storage of the shifted populations at the single-precision rate tau_R = 2 "
                           "(omega = 1.997): velocity rel L2 1.97e-3 against its own norm after 2000 steps, above "
-                          "1e-3 (tau_R 5: 1.37e-3, 10: 9.8e-4, 20: 7.2e-4)", strict=True)
+                          "1e-3 (tau_R 5: 1.37e-3, 10: 9.8e-4, 20: 7.2e-4); the oracle with its populations "
+                          "rounded to binary16 every step (the storage floor) is at 2.02e-3 itself", strict=True)
 def test_neohooke_fp16_at_the_single_precision_rate():
     print("neohooke2d D2Q9 f16 256x256 2000 steps, tau_R = 2", flush=True)
     p = inputs.PRESETS["neohooke2048"]
@@ -194,7 +198,8 @@ def test_neohooke_fp16_at_the_single_precision_rate():
     o = twin(g, p.params, parity.recipe(256, p.scaling, p.f, 2.0), Q0=[1.0, 0.0, 0.0, 1.0, 0.0, 0.0])
     o.init(Q)
     o.step(2000)
-    parity.check_fields({"F": slice(0, 4), "v": slice(4, 6)}, Qg, o.moments(), 1e-3)
+    parity.check_fields({"F": slice(0, 4), "v": slice(4, 6)}, Qg, o.moments(), 1e-3,
+                        floor=FLOOR["c5_f16_tau2"]["groups"])
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16", "f16ne"])
