@@ -14,6 +14,10 @@ Cases (argument, default all):
   c3_128   the configuration's recipe (acoustic f = 0.05, tau_R = 20,
            g_tau = 3), 500 steps of the manufactured solution with its
            forcing (SymPy residual, generated C), reference = background
+  hcnsf_f16  homogenized NSF (14 fields), D3Q7, 24^3, acoustic f = 0.05,
+           tau_R = 20, g_tau = 3, 60 steps from the manufactured state at
+           t = 0.4 with its porosity / solid-velocity field held fixed
+           (float32 values), reference = background, binary16 as for c5
   c5_f16_tau20,  neo-Hookean elastodynamics, D2Q9, 256^2, acoustic
   c5_f16_tau2    f = 0.1, tau_R = 20 (the binary16 recipe) or 2 (the
            single-precision rate), 2000 steps from inputs.neohooke_initial,
@@ -67,20 +71,21 @@ def _binary16_rounder(f0):
     return lambda f: (f * s).astype(np.float16).astype(np.float64) / s
 
 
-def floor_run(make, Q, steps, groups, report_every=100, source=None, storage="binary32"):
+def floor_run(make, Q, steps, groups, report_every=100, source=None, storage="binary32", coef=None):
     """(exact, rounded) oracle pair over `steps` (source(t): explicit source
-    at t, or None; storage: binary32, or binary16 with per-field scales);
-    returns {group: {l2, linf}}."""
+    at t, or None; storage: binary32, or binary16 with per-field scales;
+    coef: a fixed per-cell coefficient field, or None); returns
+    {group: {l2, linf}}."""
     a, b = make(), make()
-    a.init(Q)
-    b.init(Q)
+    a.init(Q, b=coef)
+    b.init(Q, b=coef)
     rnd = _binary32 if storage == "binary32" else _binary16_rounder(b.f)
     b.f = rnd(b.f)
     t0 = time.time()
     while a.nsteps < steps:
         S = None if source is None else source(a.t + 0.5 * a.dt)
-        a.step(1, source=None if S is None else (lambda t: S))
-        b.step(1, source=None if S is None else (lambda t: S))
+        a.step(1, source=None if S is None else (lambda t: S), b=coef)
+        b.step(1, source=None if S is None else (lambda t: S), b=coef)
         b.f = rnd(b.f)
         if a.nsteps % report_every == 0:
             print(f"  step {a.nsteps}/{steps} ({time.time() - t0:.0f} s)", flush=True)
@@ -130,8 +135,24 @@ def case_c5(tau_r):
             "storage": "binary16, per-field power-of-two scale", "groups": res}
 
 
+def case_hcnsf_f16():
+    n, steps, f, tau_r, g_tau = 24, 60, 0.05, 20.0, 3.0
+    dx, dt, tau = oracle.recipe(n, "acoustic", f, tau_r)
+    par = {k: inputs.PRESETS["hcnsf256"].params[k] for k in ("gamma", "mu", "kappa", "eta")}
+    coef = inputs.hcnsf_coefficients(n, 0.4).astype(np.float32).astype(np.float64)
+
+    def make():
+        return oracle.Oracle("hcnsf3d_trk14", "D3Q7", (n, n, n), dt, dx, tau, g_tau, par,
+                             Q0=np.concatenate([inputs.HCNSF_MMS.reference()[:5], np.zeros(9)]),
+                             omega_tracker=1.0 / (g_tau + 1.0))
+    groups = {"rho": slice(0, 1), "m": slice(1, 4), "E": slice(4, 5), "G_u": slice(5, 11), "G_T": slice(11, 14)}
+    res = floor_run(make, inputs.hcnsf_exact(n, 0.4), steps, groups, 20, storage="binary16", coef=coef)
+    return {"system": "hcnsf3d_trk14", "lattice": "D3Q7", "n": n, "steps": steps, "f": f, "tau_r": tau_r,
+            "g_tau": g_tau, "storage": "binary16, per-field power-of-two scale", "groups": res}
+
+
 CASES = {"c2": case_c2, "c3_64": lambda: case_c3(64), "c3_128": lambda: case_c3(128),
-         "c5_f16_tau20": lambda: case_c5(20.0), "c5_f16_tau2": lambda: case_c5(2.0)}
+         "c5_f16_tau20": lambda: case_c5(20.0), "c5_f16_tau2": lambda: case_c5(2.0), "hcnsf_f16": case_hcnsf_f16}
 
 
 def main(names):
