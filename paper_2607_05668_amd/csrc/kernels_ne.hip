@@ -75,17 +75,23 @@ __device__ inline void ne_load(const _Float16 *__restrict__ g, const float *__re
 }
 
 // The step works on a tile of kNeTX x kNeTY cells whose senders (the tile
-// and a one-cell halo, periodic) first put their stored moments and
-// lam dPhi(M) into LDS: the flux of each sender is evaluated once per
-// workgroup instead of once per pulled population (Q - 1 times per cell).
-// The receiver then rebuilds each pulled population from LDS with the same
-// float operations as the sender-side definition above.
+// and a one-cell halo, periodic) first put the parts of their equilibrium
+// into LDS: the stored moment divided by 9 (D2Q9) or 3 (D2Q5) and the two
+// components of lam dPhi(M) times w_1 / cs^2 (ExactEq::parts).  The flux and
+// the weight divisions of each sender are evaluated once per workgroup
+// instead of once per pulled population (Q - 1 times per cell); the
+// receiver finishes each pulled population's equilibrium from LDS with two
+// or three operations (ExactEq::dir), bit for bit the sender-side
+// definition above.
 constexpr int kNeTX = 64, kNeTY = 4;
 
+// periodic index of a halo row or column v in [-1, n + kNeTX]: one
+// conditional step where the tile fits the grid, a division only on grids
+// narrower than a tile
 __device__ inline int pmod(int v, int n)
 {
-    const int r = v % n;
-    return r < 0 ? r + n : r;
+    const int r = v < 0 ? v + n : v;
+    return r < n ? r : (r < 2 * n ? r - n : r % n);
 }
 
 template <class Sys, class Lat, bool NT, bool O32>
@@ -97,8 +103,8 @@ __global__ __launch_bounds__(kNeTX * kNeTY) void k_step_ne(const _Float16 *__res
     using I = typename Index<O32>::T;
     constexpr int K = Sys::K, Q = Lat::Q, D = Lat::D;
     constexpr int HX = kNeTX + 2, HY = kNeTY + 2, NH = HX * HY, NTH = kNeTX * kNeTY;
-    __shared__ float sM[K][NH];
-    __shared__ float sG[K][D][NH];
+    static_assert(D == 2, "binary16 deviation storage is built for the 2D lattices");
+    __shared__ float sP[K][3][NH];
     const size_t C = (size_t)p.C;
     const int tilesx = (p.nx + kNeTX - 1) / kNeTX;
     const unsigned t = (unsigned)xcd_tile(blockIdx.x, gridDim.x);
@@ -126,9 +132,12 @@ __global__ __launch_bounds__(kNeTX * kNeTY) void k_step_ne(const _Float16 *__res
         Sys::template flux_delta<float, float>(p.phys, My, P);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            sM[k][h] = My[k];
+            float G[D], Pt[3];
 #pragma unroll
-            for (int a = 0; a < D; ++a) sG[k][a][h] = p.lam * P[k][a];
+            for (int a = 0; a < D; ++a) G[a] = p.lam * P[k][a];
+            ExactEq<Lat>::parts(My[k], G, Pt);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) sP[k][j][h] = Pt[j];
         }
     }
     __syncthreads();
@@ -141,16 +150,10 @@ __global__ __launch_bounds__(kNeTX * kNeTY) void k_step_ne(const _Float16 *__res
         const int h = (ly + 1 - Lat::cy[i]) * HX + (lx + 1 - Lat::cx[i]);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            float ei;
-            if (i == 0) {
-                ei = ExactEq<Lat>::rest(sM[k][h]);
-            } else {
-                float G[D], e[Q];
+            float Pt[3];
 #pragma unroll
-                for (int a = 0; a < D; ++a) G[a] = sG[k][a][h];
-                ExactEq<Lat>::feq(sM[k][h], 0.0f, G, e);
-                ei = e[i];
-            }
+            for (int j = 0; j < 3; ++j) Pt[j] = sP[k][j][h];
+            const float ei = i == 0 ? ExactEq<Lat>::rest_parts(Pt) : ExactEq<Lat>::dir(Pt, i);
             f[k][i] = (float)gr[k][i] * p.inv_scale[k] + ei;
         }
     }
@@ -186,7 +189,7 @@ __global__ __launch_bounds__(kNeTX * kNeTY) void k_step_ne(const _Float16 *__res
             const float d = e[i] - f[k][i];
             const _Float16 hv = (_Float16)(fmaf(p.c1[k], d, s[i]) * p.scale[k]);
             st_pop<NT>(byte_at(gout + (size_t)(k * Q + i) * kTile, own), hv);
-            acc += (f[k][i] - e[i]) - (float)hv * p.inv_scale[k];
+            acc += (-d) - (float)hv * p.inv_scale[k];            // f - e is exactly -d
         }
         const float g0 = (f[k][0] - e0) + acc;
         st_pop<NT>(byte_at(gout + (size_t)(k * Q) * kTile, own), (_Float16)(g0 * p.scale[k]));

@@ -94,10 +94,29 @@ template <class L> struct ExactEq;
 
 template <> struct ExactEq<D2Q5> {
     template <class R> __host__ __device__ static R rest(R M) { return div_by<3>(M); }
+    template <class R> __host__ __device__ static R amp(R qh, R ql) { return qh * R(0.5) + ql * R(0.5); }
+    template <class R> __host__ __device__ static R comb(R A, R hx, R hy, int i)
+    {
+        return i == 1 ? A + hx : (i == 2 ? A + hy : (i == 3 ? A - hx : A - hy));
+    }
     template <class R> __host__ __device__ static void feq(R hi, R lo, const R *G, R *e)
     {
-        const R A = div_by<3>(hi) * R(0.5) + div_by<3>(lo) * R(0.5), hx = G[0] * R(0.5), hy = G[1] * R(0.5);
-        e[1] = A + hx; e[2] = A + hy; e[3] = A - hx; e[4] = A - hy;
+        const R A = amp(div_by<3>(hi), div_by<3>(lo)), hx = G[0] * R(0.5), hy = G[1] * R(0.5);
+#pragma unroll
+        for (int i = 1; i < 5; ++i) e[i] = comb(A, hx, hy, i);
+    }
+    // One sender's equilibrium rebuilt direction by direction (lo = 0):
+    // parts() forms its per-cell quantities once, rest_parts() and dir()
+    // finish w_0 M and e_i with the operations of rest() and feq(), so
+    // dir(parts(M, G), i) equals feq(M, 0, G)[i] bit for bit.
+    template <class R> __host__ __device__ static void parts(R M, const R *G, R *P)
+    {
+        P[0] = div_by<3>(M); P[1] = G[0] * R(0.5); P[2] = G[1] * R(0.5);
+    }
+    template <class R> __host__ __device__ static R rest_parts(const R *P) { return P[0]; }
+    template <class R> __host__ __device__ static R dir(const R *P, int i)
+    {
+        return comb(amp(P[0], div_by<3>(R(0))), P[1], P[2], i);
     }
     template <class R> __host__ __device__ static void zeroth(R s, R *e)
     {
@@ -108,13 +127,37 @@ template <> struct ExactEq<D2Q5> {
 
 template <> struct ExactEq<D2Q9> {
     template <class R> __host__ __device__ static R rest(R M) { return div_by<9>(M) * R(4); }
+    template <class R> __host__ __device__ static R amp(R qh, R ql) { return qh * R(0.25) + ql * R(0.25); }
+    template <class R> __host__ __device__ static R comb(R A, R gx, R gy, int i)
+    {
+        const R A4 = A * R(4);
+        switch (i) {
+        case 1: return A4 + gx;
+        case 2: return A4 + gy;
+        case 3: return A4 - gx;
+        case 4: return A4 - gy;
+        case 5: return A + (gx + gy) * R(0.25);
+        case 6: return A + (gy - gx) * R(0.25);
+        case 7: return A - (gx + gy) * R(0.25);
+        default: return A + (gx - gy) * R(0.25);
+        }
+    }
     template <class R> __host__ __device__ static void feq(R hi, R lo, const R *G, R *e)
     {
-        const R A = div_by<9>(hi) * R(0.25) + div_by<9>(lo) * R(0.25), A4 = A * R(4);
+        const R A = amp(div_by<9>(hi), div_by<9>(lo));
         const R gx = div_by<3>(G[0]), gy = div_by<3>(G[1]);
-        e[1] = A4 + gx; e[2] = A4 + gy; e[3] = A4 - gx; e[4] = A4 - gy;
-        e[5] = A + (gx + gy) * R(0.25); e[6] = A + (gy - gx) * R(0.25);
-        e[7] = A - (gx + gy) * R(0.25); e[8] = A + (gx - gy) * R(0.25);
+#pragma unroll
+        for (int i = 1; i < 9; ++i) e[i] = comb(A, gx, gy, i);
+    }
+    // per-sender parts and the direction-wise rebuild, as for D2Q5
+    template <class R> __host__ __device__ static void parts(R M, const R *G, R *P)
+    {
+        P[0] = div_by<9>(M); P[1] = div_by<3>(G[0]); P[2] = div_by<3>(G[1]);
+    }
+    template <class R> __host__ __device__ static R rest_parts(const R *P) { return P[0] * R(4); }
+    template <class R> __host__ __device__ static R dir(const R *P, int i)
+    {
+        return comb(amp(P[0], div_by<9>(R(0))), P[1], P[2], i);
     }
     template <class R> __host__ __device__ static void zeroth(R s, R *e)
     {

@@ -234,7 +234,11 @@ __global__ __launch_bounds__((step_block<Sys, St>())) void k_step(const St *__re
                 f[k][i] = v;
         }
     // moments (eq. moments) by compensated summation: dQ = hi + lo exactly
-    // up to the rounding of lo (two-sum of each addition)
+    // up to the rounding of lo (two-sum of each addition).  Binary16 storage
+    // sums plainly: each stored population already carries a rounding of
+    // 2^-12 of its magnitude, where the FP32 sum adds ~Q 2^-24, and the
+    // two-sums would be a fifth of the step's instructions.
+    constexpr bool COMP = Sys::compensated && !std::is_same<St, _Float16>::value;
     R dQ[K], dQlo[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -242,7 +246,7 @@ __global__ __launch_bounds__((step_block<Sys, St>())) void k_step(const St *__re
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             const R t = s + f[k][i];
-            if constexpr (Sys::compensated) {
+            if constexpr (COMP) {
                 const R bp = t - s;
                 c += (s - (t - bp)) + (f[k][i] - bp);
             }
