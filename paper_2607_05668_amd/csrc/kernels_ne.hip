@@ -154,7 +154,7 @@ __global__ __launch_bounds__(kNeTX * kNeTY) void k_step_ne(const _Float16 *__res
 #pragma unroll
             for (int j = 0; j < 3; ++j) Pt[j] = sP[k][j][h];
             const float ei = i == 0 ? ExactEq<Lat>::rest_parts(Pt) : ExactEq<Lat>::dir(Pt, i);
-            f[k][i] = (float)gr[k][i] * p.inv_scale[k] + ei;
+            f[k][i] = fmaf((float)gr[k][i], p.inv_scale[k], ei);      // the scaling is exact
         }
     }
     float dQ[K];
@@ -189,7 +189,9 @@ __global__ __launch_bounds__(kNeTX * kNeTY) void k_step_ne(const _Float16 *__res
             const float d = e[i] - f[k][i];
             const _Float16 hv = (_Float16)(fmaf(p.c1[k], d, s[i]) * p.scale[k]);
             st_pop<NT>(byte_at(gout + (size_t)(k * Q + i) * kTile, own), hv);
-            acc += (-d) - (float)hv * p.inv_scale[k];            // f - e is exactly -d
+            // f - e is exactly -d and hv / scale is exact: the closure's
+            // (f - e) - hv / scale is -(d + hv / scale), rounded once
+            acc -= fmaf((float)hv, p.inv_scale[k], d);
         }
         const float g0 = (f[k][0] - e0) + acc;
         st_pop<NT>(byte_at(gout + (size_t)(k * Q) * kTile, own), (_Float16)(g0 * p.scale[k]));
