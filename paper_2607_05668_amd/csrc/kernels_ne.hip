@@ -112,23 +112,37 @@ __global__ __launch_bounds__(kNeTX * kNeTY) void k_step_ne(const _Float16 *__res
     const int lx = (int)threadIdx.x % kNeTX, ly = (int)threadIdx.x / kNeTX;
     const int x = tx0 + lx, y = ty0 + ly;
     const bool live = x < p.nx && y < p.ny;
-    // This cell's pulled binary16 deviations do not depend on the halo work
-    // below: their loads are issued first and are in flight meanwhile.
-    _Float16 gr[K][Q];
+    // Each thread evaluates one or two halo senders (h and h + NTH).  The
+    // first sender's stored moments are loaded first, then this cell's
+    // pulled binary16 deviations, which the halo work does not need: the
+    // load counter retires in issue order, so the first halo flux
+    // evaluation waits only for its sender's moments while the deviations
+    // are still in flight.
+    static_assert(NTH <= NH && NH <= 2 * NTH, "one or two halo senders per thread");
+    const int h0 = (int)threadIdx.x, h1 = h0 + NTH;
+    auto sender = [&](int h) {
+        const int hy = h / HX, hx = h - hy * HX;
+        return (size_t)pmod(ty0 + hy - 1, p.ny) * p.nx + pmod(tx0 + hx - 1, p.nx);
+    };
+    float M0[K];
+    {
+        const size_t c0 = sender(h0);
+#pragma unroll
+        for (int k = 0; k < K; ++k) M0[k] = Min[(size_t)k * C + c0];
+    }
+    // two binary16 values per register (the d16 / d16_hi load forms)
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    h2 gr[K][(Q + 1) / 2];
     if (live) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const I src = tile_offset<K, Q>((I)wrapi(y - Lat::cy[i], p.ny) * (I)p.nx + (I)wrapi(x - Lat::cx[i], p.nx));
 #pragma unroll
-            for (int k = 0; k < K; ++k) gr[k][i] = *byte_at(gin + (size_t)(k * Q + i) * kTile, src * (I)2);
+            for (int k = 0; k < K; ++k) gr[k][i / 2][i % 2] = *byte_at(gin + (size_t)(k * Q + i) * kTile, src * (I)2);
         }
     }
-    for (int h = threadIdx.x; h < NH; h += NTH) {
-        const int hy = h / HX, hx = h - hy * HX;
-        const size_t c = (size_t)pmod(ty0 + hy - 1, p.ny) * p.nx + pmod(tx0 + hx - 1, p.nx);
-        float My[K], P[K][D];
-#pragma unroll
-        for (int k = 0; k < K; ++k) My[k] = Min[(size_t)k * C + c];
+    auto halo = [&](int h, const float *My) {
+        float P[K][D];
         Sys::template flux_delta<float, float>(p.phys, My, P);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -139,6 +153,14 @@ __global__ __launch_bounds__(kNeTX * kNeTY) void k_step_ne(const _Float16 *__res
 #pragma unroll
             for (int j = 0; j < 3; ++j) sP[k][j][h] = Pt[j];
         }
+    };
+    halo(h0, M0);
+    if (h1 < NH) {
+        float M1[K];
+        const size_t c1 = sender(h1);
+#pragma unroll
+        for (int k = 0; k < K; ++k) M1[k] = Min[(size_t)k * C + c1];
+        halo(h1, M1);
     }
     __syncthreads();
     if (!live) return;                                  // no barrier follows
@@ -154,7 +176,7 @@ __global__ __launch_bounds__(kNeTX * kNeTY) void k_step_ne(const _Float16 *__res
 #pragma unroll
             for (int j = 0; j < 3; ++j) Pt[j] = sP[k][j][h];
             const float ei = i == 0 ? ExactEq<Lat>::rest_parts(Pt) : ExactEq<Lat>::dir(Pt, i);
-            f[k][i] = fmaf((float)gr[k][i], p.inv_scale[k], ei);      // the scaling is exact
+            f[k][i] = fmaf((float)gr[k][i / 2][i % 2], p.inv_scale[k], ei);      // the scaling is exact
         }
     }
     float dQ[K];
