@@ -651,11 +651,32 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(const R *__restrict__ lin, 
     long long src[Q];
     neighbours<Lat>(x, y, z, p.nx, p.ny, p.nz, +1, src);
     const size_t C = (size_t)p.C;
+    // This cell's moments and coefficients are loaded first, then the pulled
+    // adjoint populations: the load counter retires in issue order, so the
+    // Jacobian below waits only for the moments while the populations are
+    // still in flight.
+    DK dQ[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        dQ[k] = DK(qh[(size_t)k * C + cell]);
+        dQ[k].d[k] = R(1);
+    }
+    R bl[3] = {R(0), R(0), R(0)};
+    if (p.b) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) bl[a] = p.b[(size_t)a * C + cell];
+    }
+    R mu[K][Q], M0[K], M1[K][D];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int i = 0; i < Q; ++i) mu[k][i] = lin[(size_t)(k * Q + i) * C + src[i]];
+    DK dPhi[K][D], Sk[K];
+    Sys::template flux_delta<DK, R>(p.phys, dQ, dPhi);
     // M0_k = sum_i w_i mu_{k,i} and L1_{k,a} = (lam/cs2) sum_i w_i c_ia mu_{k,i},
     // with integer weight numerators (powers of two) so that the moments
     // carry no constant rounding bias: M0 = (sum Wn_i mu_i)/Wden,
     // L1 = lam (sum Wn_i c_ia mu_i)/Fden.
-    R mu[K][Q], M0[K], M1[K][D];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         R s0 = R(0), s1[D];
@@ -663,7 +684,6 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(const R *__restrict__ lin, 
         for (int a = 0; a < D; ++a) s1[a] = R(0);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            mu[k][i] = lin[(size_t)(k * Q + i) * C + src[i]];
             const R wm = (R)Lat::Wn[i] * mu[k][i];
             s0 += wm;
 #pragma unroll
@@ -673,19 +693,6 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(const R *__restrict__ lin, 
         M0[k] = s0 / (R)Lat::Wden;
 #pragma unroll
         for (int a = 0; a < D; ++a) M1[k][a] = (p.lam * s1[a]) / (R)Lat::Fden;
-    }
-    DK dQ[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        dQ[k] = DK(qh[(size_t)k * C + cell]);
-        dQ[k].d[k] = R(1);
-    }
-    DK dPhi[K][D], Sk[K];
-    Sys::template flux_delta<DK, R>(p.phys, dQ, dPhi);
-    R bl[3] = {R(0), R(0), R(0)};
-    if (p.b) {
-#pragma unroll
-        for (int a = 0; a < D; ++a) bl[a] = p.b[(size_t)a * C + cell];
     }
     Sys::template source<DK, R>(p.phys, dQ, bl, Sk);
     // F_k: flux and source parts of Gamma_k; the relaxation part is applied in
