@@ -339,10 +339,13 @@ int lbm_restore(lbm_state *h, const void *dev_buf, long long step);
  * byte size 36 fields ceil(nx ny / 64) 64); every cell (x, y) reads plane j
  * at the periodic pull position (x, y) - c_(j mod 9) (D2Q9 order of the
  * population layout) and writes it to plane j at (x, y), one 4-byte element
- * per lane and plane, all loads of a cell issued before its stores.  fields must be 3 or 6; LBM_EINVAL otherwise or for null
- * pointers or nx, ny < 1.  Asynchronous on hip_stream.  With the step's
- * own sizes it measures what the memory system delivers for that access
- * pattern. */
+ * per lane and plane, all loads of a cell issued before its stores.  Like
+ * the step, when the two buffers exceed the 256 MiB last-level cache it
+ * stores non-temporally and (at most 300 bytes per cell, fields 3) runs its
+ * tiles in dispatch order, else in XCD-contiguous runs.  fields must be 3
+ * or 6; LBM_EINVAL otherwise or for null pointers or nx, ny < 1.
+ * Asynchronous on hip_stream.  With the step's own sizes it measures what
+ * the memory system delivers for that access pattern. */
 int lbm_bw_copy(void *dst, const void *src, size_t n, void *hip_stream);
 int lbm_bw_streams(void *dst, const void *src, int nx, int ny, int fields, void *hip_stream);
 

@@ -43,12 +43,16 @@ hipError_t lbm_launch_copy(void *dst, const void *src, size_t n, hipStream_t s)
 // The D2Q9 step's memory pattern without arithmetic, in the population
 // layout of the step (tiles of kTile cells holding all N = 9 fields planes):
 // plane j pulled from (x, y) - c_(j mod 9), periodic, and stored at (x, y).
-template <int N>
+// Like the step, a grid whose two buffers exceed the last-level cache is
+// stored non-temporally, and then (at most 300 bytes per cell) its tiles
+// run in dispatch order; cache-resident grids run XCD-contiguous tiles.
+template <int N, bool HBM>
 __global__ __launch_bounds__(kBlock) void k_streams(const float *__restrict__ src, float *__restrict__ dst, int nx,
                                                     int ny)
 {
+    constexpr bool XCD_RUNS = !(HBM && 2 * N * 4 <= 300);
     const unsigned P = (unsigned)nx * (unsigned)ny;
-    const unsigned c = (unsigned)xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const unsigned c = (XCD_RUNS ? (unsigned)xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x) * kBlock + threadIdx.x;
     if (c >= P) return;
     const int y = (int)(c / (unsigned)nx), x = (int)(c - (unsigned)y * nx);
     float v[N];
@@ -59,7 +63,7 @@ __global__ __launch_bounds__(kBlock) void k_streams(const float *__restrict__ sr
         v[j] = *byte_at(src + (size_t)j * kTile, tile_offset<N, 1>(s) * 4u);
     }
 #pragma unroll
-    for (int j = 0; j < N; ++j) *byte_at(dst + (size_t)j * kTile, tile_offset<N, 1>(c) * 4u) = v[j];
+    for (int j = 0; j < N; ++j) st_pop<HBM>(byte_at(dst + (size_t)j * kTile, tile_offset<N, 1>(c) * 4u), v[j]);
 }
 
 hipError_t lbm_launch_streams(void *dst, const void *src, int nx, int ny, int fields, hipStream_t s)
@@ -67,10 +71,12 @@ hipError_t lbm_launch_streams(void *dst, const void *src, int nx, int ny, int fi
     const size_t P = (size_t)nx * ny;
     if (padded_plane((long long)P) * 36 * fields > 0xffffffffull) return hipErrorInvalidValue;   // 32-bit byte offsets
     const dim3 grid((unsigned)((P + kBlock - 1) / kBlock));
+    const bool hbm = 2 * (size_t)padded_plane((long long)P) * 36 * fields > kLastLevelCacheBytes;
+    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, (const float *)src, (float *)dst, nx, ny); };
     if (fields == 3)
-        hipLaunchKernelGGL(k_streams<27>, grid, dim3(kBlock), 0, s, (const float *)src, (float *)dst, nx, ny);
+        hbm ? go(k_streams<27, true>) : go(k_streams<27, false>);
     else if (fields == 6)
-        hipLaunchKernelGGL(k_streams<54>, grid, dim3(kBlock), 0, s, (const float *)src, (float *)dst, nx, ny);
+        hbm ? go(k_streams<54, true>) : go(k_streams<54, false>);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
