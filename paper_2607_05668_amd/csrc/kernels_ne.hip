@@ -130,7 +130,8 @@ __global__ __launch_bounds__(kNeTX * kNeTY) void k_step_ne(const _Float16 *__res
 #pragma unroll
         for (int k = 0; k < K; ++k) M0[k] = Min[(size_t)k * C + c0];
     }
-    // two binary16 values per register (the d16 / d16_hi load forms)
+    // two binary16 values per register: the deviations then hold 27 of the
+    // kernel's registers instead of 54 (four waves per SIMD, not three)
     typedef _Float16 h2 __attribute__((ext_vector_type(2)));
     h2 gr[K][(Q + 1) / 2];
     if (live) {
